@@ -1,0 +1,168 @@
+"""Benchmark: log-likelihood + gradient pairs/s at N = 1e6 on one MI355X.
+
+One step = one pass of the hot path over the 1e6-event workload (1200 days,
+3000 rectangular counties, LogNormal(5, 1.5) densities): redraw every latent
+location uniformly inside its county (the cut-posterior X-update), then one
+fused FP32 log-likelihood + 6-gradient evaluation with FP64 finalize.
+Inputs are synthetic and resident in HBM before timing starts.
+
+Prints one JSON line.  Extra fields: the same evaluation in the FP64 sweep,
+the roofline of the dominant kernel (pair sweep), and the FP64 CPU oracle
+timed on a bounded sample of target rows on the host cores.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "loglik+grad pairs/s at N=1M, FP32 vs FP64; ESS/s surrogate-HMC vs plain HMC"
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector: 256 CU x 2.4 GHz x 256 FLOP/clk
+# algorithmic FLOP per pair of the fused sweep (FMA = 2, add/sub/mul = 1; exp counted apart):
+# background 15 for every pair, triggering 10 more for causal pairs
+FLOP_BG, FLOP_TRIG = 15, 10
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def pair_counts(t: np.ndarray) -> tuple[int, int]:
+    """(background pairs, causal pairs) with ties excluded, from sorted times."""
+    lo = np.searchsorted(t, t, side="left")
+    hi = np.searchsorted(t, t, side="right")
+    n = t.shape[0]
+    causal = int(lo.sum())
+    bg = int((n - (hi - lo)).sum())
+    return bg, causal
+
+
+def cpu_baseline(ev, th, budget_s: float = 15.0) -> dict:
+    """The FP64 oracle on a bounded sample of target rows x all sources."""
+    import oracle
+
+    n = ev.n
+    probe = 200
+    t0 = time.perf_counter()
+    oracle.loglik(ev.t, ev.x, ev.y, ev.s, th, rows=(n // 2, n // 2 + probe))
+    dt = time.perf_counter() - t0
+    rows = int(max(probe, min(n, probe * budget_s / max(dt, 1e-3))))
+    r0 = (n - rows) // 2
+    t0 = time.perf_counter()
+    oracle.loglik(ev.t, ev.x, ev.y, ev.s, th, rows=(r0, r0 + rows))
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": rows * (n - 1) / dt, "unit": "pairs/s", "cores": cores, "kind": "oracle",
+            "sample": f"{rows} target rows (middle of the time range) x {n} sources, loglik+grad, FP64, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=None, help="override the event count (testing only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the pair sweep of one GPU is the measured unit; "
+              "a multi-GPU row split is described in DESIGN.md but not run here.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    import paper_2407_11349_amd as hk
+
+    cfg = synth.CONFIGS[2]
+    ev = synth.generate(cfg, n=args.n)
+    th = synth.theta_default()
+    n = ev.n
+    dev = hk.DeviceEvents.from_arrays(ev.t, ev.x, ev.y, ev.s, device="cuda")
+    county = torch.from_numpy(ev.county).cuda()
+    rect = torch.from_numpy(ev.rect).cuda()
+    ws = hk.Workspace(n, "fp32")
+    out_ll = torch.empty(1, dtype=torch.float64, device="cuda")
+    out_g = torch.empty(6, dtype=torch.float64, device="cuda")
+    seed = 2002
+    bg_pairs, causal_pairs = pair_counts(ev.t)
+    flop_per_launch = FLOP_BG * bg_pairs + FLOP_TRIG * causal_pairs
+    exp_per_launch = bg_pairs + causal_pairs
+
+    def step(it):
+        hk.resample_locations(county, rect, seed, it, dev.x, dev.y)
+        hk.loglik_grad(dev, th, precision="fp32", ws=ws, out=out_ll, grad=out_g)
+
+    log(f"bench: n={n} warmup={args.warmup} steps={args.steps}")
+    for it in range(args.warmup):
+        step(it)
+        torch.cuda.synchronize()
+        log(f"warmup step {it} done: loglik {out_ll.item():.6f}")
+
+    hk.set_timing(True)
+    kernel_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(args.warmup + k)
+        kernel_ms.append(hk.last_pair_kernel_ms())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    hk.set_timing(False)
+    log(f"timed {args.steps} steps in {elapsed:.3f} s; pair kernel ms {['%.2f' % v for v in kernel_ms]}")
+    ll_last = float(out_ll.item())
+    assert np.isfinite(ll_last) and ws.status() == 0
+
+    ms_step = elapsed / args.steps * 1e3
+    pairs = n * (n - 1)
+    value = pairs / (ms_step / 1e3)
+    kms = float(np.mean(kernel_ms))
+    achieved = flop_per_launch / (kms / 1e3) / 1e12
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": cfg.name, "n_events": n, "days": cfg.t_max, "counties": cfg.nx * cfg.ny,
+                   "rho_sdlog": cfg.rho_sdlog, "step": "resample X + FP32 loglik+grad (FP64 finalize)",
+                   "parallelism": "single GPU"},
+        "loglik_grad_evals_per_s": 1e3 / ms_step,
+        "roofline": {"bound": "alu", "kernel": "k_pair_f32<grad>", "achieved": achieved,
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": None, "kernel_ms": kms, "flop_per_launch": flop_per_launch,
+                     "exp_per_launch": exp_per_launch, "exp_per_s": exp_per_launch / (kms / 1e3)},
+    }
+
+    if not args.no_fp64:
+        ws64 = hk.Workspace(n, "fp64")
+        hk.loglik_grad(dev, th, precision="fp64", ws=ws64, out=out_ll, grad=out_g)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        hk.loglik_grad(dev, th, precision="fp64", ws=ws64, out=out_ll, grad=out_g)
+        torch.cuda.synchronize()
+        d64 = time.perf_counter() - t1
+        result["fp64"] = {"value": pairs / d64, "unit": "pairs/s", "ms_per_eval": d64 * 1e3,
+                          "fp32_speedup": (pairs / (ms_step / 1e3)) / (pairs / d64)}
+        log(f"fp64 evaluation: {d64 * 1e3:.1f} ms")
+        del ws64
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(ev, th)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,150 @@
+/*
+ * hawkes.h -- C ABI of the MI355X (gfx950) spatiotemporal Hawkes likelihood
+ * library (libhawkes.so).
+ *
+ * The model is the one of Ko, Suchard and Holbrook, "Scaling Hawkes processes
+ * to one million COVID-19 cases" (arXiv 2407.11349), Section 2.1: for events
+ * (x_n, t_n), n = 1..N, sorted by time,
+ *
+ *   lambda_n = mu * sum_{m: t_m != t_n} N2(|x_n - x_m|^2; tau_x^2) N1(t_n - t_m; tau_t^2)
+ *            + xi * sum_{m: t_m <  t_n} N2(|x_n - x_m|^2; h_m^2) omega exp(-omega (t_n - t_m)),
+ *   h_m      = h0 * s_m      (per-source spatial sd; equation "varying" uses
+ *                             s_m = D_m^(-1/2) for the county population density D_m),
+ *   Lambda_n = mu [Phi((t_N - t_n)/tau_t) - Phi(-t_n/tau_t)] + xi [1 - exp(-omega (t_N - t_n))]
+ *              (the compensator over the time domain (0, t_N] after the R^2 approximation),
+ *   l_n      = log(max(lambda_n, 1e-40)) - Lambda_n   (the floor of Section 2.3.1),
+ *
+ * where N2(r^2; v) is the isotropic bivariate normal density with variance v
+ * per axis and N1(d; v) the univariate normal density.  Self pairs and exact
+ * time ties are excluded from both sums.  The log-likelihood of rows
+ * [row_begin, row_end) is sum_{n in rows} l_n; the full range gives equation
+ * "model", and any split of it adds up to the full value (the per-GPU slices
+ * of Section 2.3.2).
+ *
+ * Conventions for every call:
+ *  - All array arguments are DEVICE pointers on the current HIP device,
+ *    borrowed for the duration of the call; the caller owns them.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *    asynchronously on it; outputs are valid after the caller synchronises.
+ *  - No call allocates device memory: scratch space comes from the
+ *    caller-provided workspace `ws` of at least hawkes_workspace_bytes() bytes,
+ *    256-byte aligned.  Calls that share a workspace must not overlap.
+ *  - Return value: HAWKES_OK (0) or a negative status; no C++ exception
+ *    crosses the ABI.  hawkes_last_error() gives a message for the calling
+ *    thread's last failure.
+ *  - Argument checks done on the host return an error before any work is
+ *    enqueued.  Data checks (times sorted, values finite, s > 0) run on the
+ *    device: on failure the outputs are set to NaN and the status word in the
+ *    workspace records the reason (hawkes_workspace_status).
+ */
+#ifndef HAWKES_H
+#define HAWKES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Model parameters in natural units: mu (-), tau_x (km), tau_t (days), xi (-),
+ * h0 (km), omega (1/day).  All must be finite and > 0. */
+typedef struct hawkes_theta {
+    double mu, tau_x, tau_t, xi, h0, omega;
+} hawkes_theta;
+
+/* One event set: n events, all arrays device-resident, length n, FP64.
+ * t must be nondecreasing (t_N = t[n-1]); s is the per-event bandwidth scale
+ * (> 0): 1 for the paper's model 1, D_n^(-1/2) for its model 2. */
+typedef struct hawkes_events {
+    int64_t n;
+    const double *t;
+    const double *x;
+    const double *y;
+    const double *s;
+} hawkes_events;
+
+/* Arithmetic of the O(N^2) pair sweep.  FP64: every pair term in FP64.
+ * FP32: pair terms in FP32 (pair differences formed in FP64 and rounded once,
+ * per-tile FP32 partial sums folded into FP64 accumulators); the per-event
+ * log, the compensator and all reductions stay in FP64. */
+enum hawkes_precision { HAWKES_FP64 = 0, HAWKES_FP32 = 1 };
+
+enum hawkes_status {
+    HAWKES_OK = 0,
+    HAWKES_EINVAL = -1,     /* null pointer, n < 1, n too large, bad precision, theta not finite/positive */
+    HAWKES_ERANGE = -2,     /* not 0 <= row_begin <= row_end <= n */
+    HAWKES_EWORKSPACE = -3, /* workspace null, misaligned or smaller than hawkes_workspace_bytes() */
+    HAWKES_EHIP = -4,       /* a HIP runtime call failed; see hawkes_last_error() */
+    HAWKES_EORDER = -5,     /* device check: times not nondecreasing */
+    HAWKES_EDATA = -6       /* device check: a non-finite value or s <= 0 */
+};
+
+/* Bytes of workspace the likelihood calls need for n events at `precision`
+ * (0 if the arguments are invalid).  Grows linearly with n. */
+size_t hawkes_workspace_bytes(int64_t n, int precision);
+
+/* Log-likelihood of rows [row_begin, row_end):  *d_loglik = sum_n l_n
+ * (paper equation "model").  d_loglik: device pointer to 1 double.
+ * Empty row ranges give 0. */
+int hawkes_loglik(const hawkes_events *events, const hawkes_theta *theta, int precision,
+                  int64_t row_begin, int64_t row_end, void *ws, size_t ws_bytes,
+                  double *d_loglik, void *stream);
+
+/* As hawkes_loglik, plus the gradient of the same row sum with respect to
+ * theta, in the order (mu, tau_x, tau_t, xi, h0, omega): d_grad is a device
+ * pointer to 6 doubles.  Forward and adjoint sums come from one fused pass
+ * over the pairs.  A floored event contributes no gradient from its log term. */
+int hawkes_loglik_grad(const hawkes_events *events, const hawkes_theta *theta, int precision,
+                       int64_t row_begin, int64_t row_end, void *ws, size_t ws_bytes,
+                       double *d_loglik, double *d_grad, void *stream);
+
+/* Per-event terms of rows [row_begin, row_end): d_lambda[r] = lambda_n and
+ * d_comp[r] = Lambda_n for n = row_begin + r (device arrays of
+ * row_end - row_begin doubles; either may be NULL).  Uses the same pair
+ * sweep as hawkes_loglik. */
+int hawkes_event_terms(const hawkes_events *events, const hawkes_theta *theta, int precision,
+                       int64_t row_begin, int64_t row_end, void *ws, size_t ws_bytes,
+                       double *d_lambda, double *d_comp, void *stream);
+
+/* The X-update of the cut posterior (paper Section 2.2: latent locations drawn
+ * from p(X | coarsened data) in O(N), uniformly within each event's county),
+ * with counties as axis-aligned rectangles.
+ *   d_county  device int32[n], county id of each event in [0, n_counties)
+ *   d_rect    device double[n_counties * 4], rows (x0, y0, x1, y1), x0 < x1, y0 < y1
+ *   seed, iteration  Philox4x64-10 key (seed, 0) and counter (n, iteration, 0, 0)
+ *   d_x, d_y  device double[n] outputs (may alias the event arrays)
+ * Event i gets u = (w >> 11) * 2^-53 from output words 0 and 1 and
+ * x = fma(u, x1 - x0, x0) (likewise y), so results are bit-reproducible.
+ * An out-of-range county id leaves that event's location as NaN. */
+int hawkes_resample_locations(int64_t n, const int32_t *d_county, const double *d_rect,
+                              int32_t n_counties, uint64_t seed, uint64_t iteration,
+                              double *d_x, double *d_y, void *stream);
+
+/* Synchronises `stream` and reads the device status word of workspace `ws`
+ * written by the last likelihood call that used it: *status = HAWKES_OK,
+ * HAWKES_EORDER or HAWKES_EDATA. */
+int hawkes_workspace_status(const void *ws, int *status, void *stream);
+
+/* Timing of the dominant pair-sweep kernel: when enabled, each likelihood
+ * call records HIP events around that kernel on the caller's stream, and
+ * hawkes_last_pair_kernel_ms() waits for the last one and returns its
+ * duration in milliseconds. */
+int hawkes_set_timing(int enable);
+int hawkes_last_pair_kernel_ms(float *ms);
+
+/* Tuning: the number of workgroups the pair sweep aims for per call (the
+ * source range is split into chunks so that target blocks x chunks is about
+ * this many; 1 <= wgs <= 16384; default 4096).  Results do not depend on it
+ * beyond FP rounding of the chunk partial sums.  Process-wide setting. */
+int hawkes_tune_target_workgroups(int64_t wgs);
+
+/* Message for a status code, and the calling thread's last error message. */
+const char *hawkes_strerror(int status);
+const char *hawkes_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HAWKES_H */

@@ -1,0 +1,115 @@
+"""ctypes binding of libhawkes.so: argument marshalling only.
+
+Every step of the likelihood runs in the HIP library; this module converts
+torch tensors (device memory, streams) into the plain pointers and sizes of
+the C ABI in include/hawkes.h, and raises on a non-zero status.  If the
+library has not been built, loading fails loudly; there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+import torch
+
+LIB_PATH = Path(__file__).resolve().parent / "libhawkes.so"
+
+HAWKES_FP64 = 0
+HAWKES_FP32 = 1
+PRECISIONS = {"fp64": HAWKES_FP64, "fp32": HAWKES_FP32, HAWKES_FP64: HAWKES_FP64, HAWKES_FP32: HAWKES_FP32}
+
+HAWKES_OK = 0
+HAWKES_EORDER = -5
+HAWKES_EDATA = -6
+
+# every entry point declared in include/hawkes.h
+EXPORTS = (
+    "hawkes_workspace_bytes", "hawkes_loglik", "hawkes_loglik_grad", "hawkes_event_terms",
+    "hawkes_resample_locations", "hawkes_workspace_status", "hawkes_set_timing",
+    "hawkes_last_pair_kernel_ms", "hawkes_tune_target_workgroups", "hawkes_strerror", "hawkes_last_error",
+)
+
+
+class Theta(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("mu", "tau_x", "tau_t", "xi", "h0", "omega")]
+
+
+class Events(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("t", ctypes.c_void_p), ("x", ctypes.c_void_p),
+                ("y", ctypes.c_void_p), ("s", ctypes.c_void_p)]
+
+
+class HawkesError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: status {status}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: Path | str | None = None) -> ctypes.CDLL:
+    """Load libhawkes.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = Path(path) if path is not None else LIB_PATH
+    if not p.exists():
+        raise RuntimeError(f"{p} is not built; run paper_2407_11349_amd.build.build_library() first")
+    lib = ctypes.CDLL(str(p))
+    vp, i64, i32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64
+    ev_p, th_p = ctypes.POINTER(Events), ctypes.POINTER(Theta)
+    lib.hawkes_workspace_bytes.argtypes = [i64, ctypes.c_int]
+    lib.hawkes_workspace_bytes.restype = ctypes.c_size_t
+    common = [ev_p, th_p, ctypes.c_int, i64, i64, vp, ctypes.c_size_t]
+    lib.hawkes_loglik.argtypes = common + [vp, vp]
+    lib.hawkes_loglik_grad.argtypes = common + [vp, vp, vp]
+    lib.hawkes_event_terms.argtypes = common + [vp, vp, vp]
+    lib.hawkes_resample_locations.argtypes = [i64, vp, vp, i32, u64, u64, vp, vp, vp]
+    lib.hawkes_workspace_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int), vp]
+    lib.hawkes_set_timing.argtypes = [ctypes.c_int]
+    lib.hawkes_last_pair_kernel_ms.argtypes = [ctypes.POINTER(ctypes.c_float)]
+    lib.hawkes_tune_target_workgroups.argtypes = [i64]
+    lib.hawkes_strerror.argtypes = [ctypes.c_int]
+    lib.hawkes_strerror.restype = ctypes.c_char_p
+    lib.hawkes_last_error.argtypes = []
+    lib.hawkes_last_error.restype = ctypes.c_char_p
+    for name in ("hawkes_loglik", "hawkes_loglik_grad", "hawkes_event_terms", "hawkes_resample_locations",
+                 "hawkes_workspace_status", "hawkes_set_timing", "hawkes_last_pair_kernel_ms",
+                 "hawkes_tune_target_workgroups"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def check(status: int, where: str) -> None:
+    if status != HAWKES_OK:
+        lib = load()
+        raise HawkesError(status, where, lib.hawkes_last_error().decode() or lib.hawkes_strerror(status).decode())
+
+
+def precision_code(precision) -> int:
+    try:
+        return PRECISIONS[precision]
+    except KeyError:
+        raise ValueError(f"unknown precision {precision!r}") from None
+
+
+def stream_handle(stream: torch.cuda.Stream | None = None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def theta_struct(theta) -> Theta:
+    if isinstance(theta, torch.Tensor):
+        vals = theta.detach().to("cpu", torch.float64).tolist()
+    else:
+        vals = [float(v) for v in theta]
+    if len(vals) != 6:
+        raise ValueError("theta must have 6 components (mu, tau_x, tau_t, xi, h0, omega)")
+    return Theta(*vals)
+
+
+def ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else int(t.data_ptr())

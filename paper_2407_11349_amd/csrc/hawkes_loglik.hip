@@ -1,0 +1,1310 @@
+// hawkes_loglik.hip -- O(N^2) spatiotemporal Hawkes log-likelihood and its
+// gradient on gfx950 (MI355X), behind the C ABI declared in include/hawkes.h.
+//
+// Model: paper Section 2.1 (equations "fixed", "varying", "model" and the
+// compensator after the R^2 approximation); floor of Section 2.3.1; row
+// slices of Section 2.3.2.  See include/hawkes.h for the exact definition.
+//
+// Pipeline of one call (all on the caller's stream, no allocation):
+//   1. k_clear_status, k_stage_common   tie-group ids, tile time ranges, data checks
+//   2. k_stage_f32 (FP32 only)          per-theta source records in SoA layout
+//   3. k_pair_f32 / k_pair_f64          the pair sweep: per target row, six sums
+//                                       over all sources of one source chunk
+//   4. k_finalize                       per row: lambda_n, log, gradient terms,
+//                                       compensator (FP64); FP32 rows whose sums
+//                                       are underflow-limited go on a rescue list
+//   5. k_rescue                         those rows again, every pair in FP64
+//   6. k_blocksum, k_reduce             fixed-order FP64 sums of the row values
+//
+// Pair sums of target n (App. A of the design notes; u_m = s_m^-2):
+//   S0 = sum_{t_m != t_n} b_nm,  Sd2 = sum b d^2,  Sdt2 = sum b dt^2,
+//   G0 = sum_{t_m < t_n} u_m e_nm,  G1 = sum u_m e (u_m d^2),  G2 = sum u_m e dt,
+//   b_nm = exp(-d^2/(2 tau_x^2) - dt^2/(2 tau_t^2)),  e_nm = exp(-u_m d^2/(2 h0^2) - omega dt).
+// With c_b = 1/((2 pi)^1.5 tau_x^2 tau_t) and c_g = omega/(2 pi h0^2):
+//   lambda_n = mu c_b S0 + xi c_g G0, and every d lambda_n / d theta is a
+//   linear combination of the six sums.
+//
+// Work decomposition: a workgroup owns TB = 1024 target rows (4 per lane) and
+// one chunk of source tiles; TS = 256 sources per tile are staged through LDS
+// (double buffered) and read by all lanes as broadcasts.  Each
+// (target block, tile) pair is classified from the tile's and the block's
+// time ranges: CAUSAL (every source strictly earlier than every target:
+// background + triggering, no masks), ANTI (every source strictly later:
+// background only) or MIXED (per-pair masks from tie-group ids).  Causality
+// is never decided from rounded times.
+//
+// FP32 arithmetic (precision HAWKES_FP32):
+//  * positions are pre-scaled in FP64 by sqrt(log2(e)/(2 tau_x^2)) and times
+//    by sqrt(log2(e)/(2 tau_t^2)); the background exponent A = d2 + dt^2 is
+//    formed in FP64 from them and rounded once, so no rounded per-theta
+//    constant and no rounded time difference (integer-day data have only a
+//    few distinct ones) enters the background;
+//  * the triggering time factor is split at the tile's last time T_k:
+//    exp(-omega dt) = exp(-omega (t_n - T_k)) * exp(-omega (T_k - t_m)); the
+//    source factor is folded into v_m = u_m exp(-omega (T_k - t_m)) at
+//    staging and the target factor is applied in FP64 per tile;
+//  * each tile's 256-term FP32 partial sums are folded into FP64 accumulators.
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+
+#include "hawkes.h"
+#include "hawkes_common.h"
+
+namespace hawkes {
+
+namespace {
+
+constexpr int TS = 256;                   // sources per LDS tile
+constexpr int WG = 256;                   // threads per workgroup (4 wave64)
+constexpr int KT = 4;                     // target rows per lane
+constexpr int TB = WG * KT;               // target rows per workgroup
+constexpr int GS = 8;                     // FP32 terms summed before folding into FP64
+constexpr int64_t MAX_TARGET_WGS = 16384; // upper bound used for workspace sizing
+constexpr int64_t MAX_N = int64_t(1) << 30;
+constexpr double LOG2E = 1.4426950408889634074;
+constexpr double LAMBDA_FLOOR = 1e-40;
+constexpr double PAD_COORD = 1e15;        // padding sources sit far away: their terms are exactly 0
+
+// Mean relative error of v_exp_f32 on gfx950, measured over 2^30 FP32
+// arguments spread uniformly on [-30, 0] (and, to within 2e-10, on [-12, 0]
+// and [-100, -30]): every FP32 pair term carries exactly one hardware exp2,
+// so the FP32 sums are divided by (1 + this) in FP64.
+constexpr double EXP2_MEAN_REL_ERR = -3.41e-9;
+// Rows whose FP32 rate may have lost more than this fraction of its value to
+// FP32 underflow (terms below 2^-126) are recomputed in FP64.
+constexpr double RESCUE_REL = 1e-12;
+
+constexpr int STATUS_ORDER = 1;
+constexpr int STATUS_DATA = 2;
+
+enum TileClass { CAUSAL = 0, ANTI = 1, MIXED = 2 };
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------------------------ layout
+
+struct Layout {
+    int64_t n = 0, n_pad = 0, num_tiles = 0, part_elems = 0, max_blocks = 0, rows_cap = 0;
+    size_t status = 0, g = 0, tile = 0, rowvals = 0, rescue = 0;
+    size_t xs = 0, ys = 0, tsd = 0, rh = 0, rl = 0, vh = 0, vl = 0, dl = 0, uh = 0, ul = 0;
+    size_t partials = 0, blocks = 0, total = 0;
+};
+
+Layout make_layout(int64_t n, int precision)
+{
+    Layout L;
+    L.n = n;
+    L.num_tiles = ceil_div(n, TS);
+    L.n_pad = L.num_tiles * TS;
+    const int64_t tb_max = ceil_div(n, TB);
+    int64_t slots = L.num_tiles * tb_max;
+    if (slots > MAX_TARGET_WGS + tb_max)
+        slots = MAX_TARGET_WGS + tb_max;
+    L.part_elems = slots * TB * 6;
+    L.max_blocks = ceil_div(n, WG);
+    L.rows_cap = tb_max * TB;
+
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    L.status = take(256);
+    L.g = take(sizeof(int) * L.n_pad);
+    L.tile = take(sizeof(double) * 3 * L.num_tiles);
+    if (precision == HAWKES_FP32) {
+        L.xs = take(sizeof(double) * L.n_pad);
+        L.ys = take(sizeof(double) * L.n_pad);
+        L.tsd = take(sizeof(double) * L.n_pad);
+        L.rh = take(sizeof(float) * L.n_pad);
+        L.rl = take(sizeof(float) * L.n_pad);
+        L.vh = take(sizeof(float) * L.n_pad);
+        L.vl = take(sizeof(float) * L.n_pad);
+        L.dl = take(sizeof(float) * L.n_pad);
+        L.uh = take(sizeof(float) * L.n_pad);
+        L.ul = take(sizeof(float) * L.n_pad);
+    }
+    L.partials = take(sizeof(double) * L.part_elems);
+    L.blocks = take(sizeof(double) * 7 * L.max_blocks);
+    L.rowvals = take(sizeof(double) * 7 * L.rows_cap);
+    L.rescue = take(sizeof(int) * L.rows_cap);
+    L.total = off;
+    return L;
+}
+
+// Work plan of one call: target blocks over the row range, source chunks.
+struct Plan {
+    int64_t rows = 0, num_tb = 0, rows_pad = 0, chunk_tiles = 0, num_chunks = 0;
+};
+
+int64_t g_target_wgs = 4096;
+
+Plan make_plan(int64_t rows, int64_t num_tiles)
+{
+    Plan P;
+    P.rows = rows;
+    P.num_tb = ceil_div(rows, TB);
+    P.rows_pad = P.num_tb * TB;
+    int64_t want = ceil_div(g_target_wgs, P.num_tb);
+    if (want < 1)
+        want = 1;
+    if (want > num_tiles)
+        want = num_tiles;
+    P.chunk_tiles = ceil_div(num_tiles, want);
+    P.num_chunks = ceil_div(num_tiles, P.chunk_tiles);
+    return P;
+}
+
+// ------------------------------------------------------------- kernels
+
+// status[0]: data-check flags; status[1]: number of rows on the rescue list
+__global__ void k_clear_status(int *status)
+{
+    status[0] = 0;
+    status[1] = 0;
+}
+
+__global__ void k_zero_outputs(double *loglik, double *grad)
+{
+    const int i = threadIdx.x;
+    if (i == 0 && loglik)
+        loglik[0] = 0.0;
+    if (i < 6 && grad)
+        grad[i] = 0.0;
+}
+
+// Tie-group ids (index of the first event with the same time), tile time
+// ranges, and the device-side data checks.
+__global__ __launch_bounds__(256) void k_stage_common(const double *__restrict__ t, const double *__restrict__ x,
+                                                      const double *__restrict__ y, const double *__restrict__ s,
+                                                      int64_t n, int64_t n_pad, int *__restrict__ g,
+                                                      double *__restrict__ tile, int *status)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n_pad)
+        return;
+    if (i >= n) {
+        g[i] = INT_MAX;
+        return;
+    }
+    const double ti = t[i];
+    int flags = 0;
+    if (!isfinite(ti) || !isfinite(x[i]) || !isfinite(y[i]) || !isfinite(s[i]) || !(s[i] > 0.0))
+        flags |= STATUS_DATA;
+    if (i + 1 < n && t[i + 1] < ti)
+        flags |= STATUS_ORDER;
+    if (flags)
+        atomicOr(status, flags);
+    // lower bound of ti in the (sorted) time array
+    int64_t lo = 0, hi = i;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (t[mid] < ti)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    g[i] = int(lo);
+    if (i % TS == 0) {
+        const int64_t k = i / TS;
+        const int64_t last = (i + TS < n ? i + TS : n) - 1;
+        tile[3 * k + 0] = ti;
+        tile[3 * k + 1] = t[last];
+    }
+}
+
+struct StageF32 {
+    double sx, st, rr, omega;
+};
+
+// Splits an FP64 value into an FP32 pair hi + lo (hi = nearest FP32).
+__device__ inline void split_f32(double v, float &hi, float &lo)
+{
+    hi = float(v);
+    lo = float(v - double(hi));
+}
+
+// Per-theta source records for the FP32 sweep (SoA, padded to whole tiles):
+// positions and times pre-scaled in FP64; r_m = u_m (tau_x/h0)^2,
+// v_m = u_m exp(-omega (T_k - t_m)) and u_m as FP32 hi + lo pairs, so that
+// no rounding is shared by many pairs (all sources of the paper's model 1
+// have one u; integer-day times give few distinct T_k - t_m).
+__global__ __launch_bounds__(256) void k_stage_f32(const double *__restrict__ t, const double *__restrict__ x,
+                                                   const double *__restrict__ y, const double *__restrict__ s,
+                                                   int64_t n, int64_t n_pad, StageF32 c,
+                                                   const double *__restrict__ tile, double *__restrict__ xs,
+                                                   double *__restrict__ ys, double *__restrict__ tsd,
+                                                   float *__restrict__ rh, float *__restrict__ rl,
+                                                   float *__restrict__ vh, float *__restrict__ vl,
+                                                   float *__restrict__ dl, float *__restrict__ uh,
+                                                   float *__restrict__ ul)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n_pad)
+        return;
+    if (i >= n) {
+        xs[i] = PAD_COORD;
+        ys[i] = PAD_COORD;
+        tsd[i] = 0.0;
+        rh[i] = rl[i] = vh[i] = vl[i] = dl[i] = uh[i] = ul[i] = 0.0f;
+        return;
+    }
+    const int64_t k = i / TS;
+    const double tlast = tile[3 * k + 1];
+    const double si = s[i];
+    const double u = 1.0 / (si * si);
+    const double d = tlast - t[i];
+    xs[i] = x[i] * c.sx;
+    ys[i] = y[i] * c.sx;
+    tsd[i] = t[i] * c.st;
+    float hi, lo;
+    split_f32(u * c.rr, hi, lo);
+    rh[i] = hi;
+    rl[i] = lo;
+    split_f32(u * exp(-c.omega * d), hi, lo);
+    vh[i] = hi;
+    vl[i] = lo;
+    split_f32(u, hi, lo);
+    uh[i] = hi;
+    ul[i] = lo;
+    dl[i] = float(d);
+}
+
+struct PairF32 {
+    const double *xs, *ys, *tsd, *t;
+    const float *rh, *rl, *vh, *vl, *dl, *uh, *ul;
+    const int *g;
+    const double *tile;
+    double *partials;
+    int64_t row_begin, row_end, rows_pad, num_tiles, chunk_tiles, num_chunks, num_tb;
+    double omega, inv_st, out_s1, out_s2, out_g1, out_exp;
+    double w2;  // omega * log2(e) / time scale: the triggering exponent per scaled day
+};
+
+// The FP32 fused sweep.  GRAD = false keeps only S0 and G0 (log-likelihood).
+//
+// Per pair (positions and times pre-scaled so that the background exponent
+// is A = |x_n - x_m|^2 + (t_n - t_m)^2):
+//   d2 = |x_n - x_m|^2 and A = d2 + dt^2 in FP64, each rounded once to FP32;
+//   background b = exp2(-A); triggering (earlier sources) p = v_m exp2(-t1)
+//   with t1 = r_m D.  Every FP32 value that many pairs would share is split
+//   hi + lo, and every rounding left is of a value that varies from pair to
+//   pair, so rounding errors average out instead of adding up.
+template <bool GRAD>
+__global__ __launch_bounds__(WG) void k_pair_f32(PairF32 a)
+{
+    __shared__ double lx[2][TS], ly[2][TS], lt[2][TS];
+    __shared__ float lrh[2][TS], lrl[2][TS], lvh[2][TS], lvl[2][TS], ld[2][TS], luh[2][TS], lul[2][TS];
+    __shared__ int lg[2][TS];
+
+    const int tid = threadIdx.x;
+    const int64_t tbr = blockIdx.x / a.num_chunks;
+    const int64_t chunk = blockIdx.x - tbr * a.num_chunks;
+    const int64_t tb = a.num_tb - 1 - tbr;  // latest (most expensive) target blocks first
+    const int64_t i0 = a.row_begin + tb * TB;
+    const int64_t iend = (i0 + TB < a.row_end) ? i0 + TB : a.row_end;
+    const double t_lo = a.t[i0], t_hi = a.t[iend - 1];
+
+    double xn[KT], yn[KT], tsn[KT], trn[KT];
+    int gn[KT];
+#pragma unroll
+    for (int q = 0; q < KT; ++q) {
+        int64_t i = i0 + tid + q * WG;
+        if (i >= iend)
+            i = iend - 1;
+        xn[q] = a.xs[i];
+        yn[q] = a.ys[i];
+        tsn[q] = a.tsd[i];
+        trn[q] = a.t[i];
+        gn[q] = a.g[i];
+    }
+    double acc[KT][6];
+#pragma unroll
+    for (int q = 0; q < KT; ++q)
+#pragma unroll
+        for (int z = 0; z < 6; ++z)
+            acc[q][z] = 0.0;
+
+    const int64_t k0 = chunk * a.chunk_tiles;
+    const int64_t k1 = (k0 + a.chunk_tiles < a.num_tiles) ? k0 + a.chunk_tiles : a.num_tiles;
+
+    struct Rec {
+        double x, y, t;
+        float rh, rl, vh, vl, d, uh, ul;
+        int g;
+    };
+    auto fetch = [&](int64_t k) {
+        const int64_t j = k * TS + tid;
+        return Rec{a.xs[j], a.ys[j], a.tsd[j], a.rh[j], a.rl[j], a.vh[j], a.vl[j], a.dl[j], a.uh[j], a.ul[j], a.g[j]};
+    };
+    auto store = [&](const Rec &r, int buf) {
+        lx[buf][tid] = r.x;
+        ly[buf][tid] = r.y;
+        lt[buf][tid] = r.t;
+        lrh[buf][tid] = r.rh;
+        lrl[buf][tid] = r.rl;
+        lvh[buf][tid] = r.vh;
+        lvl[buf][tid] = r.vl;
+        ld[buf][tid] = r.d;
+        luh[buf][tid] = r.uh;
+        lul[buf][tid] = r.ul;
+        lg[buf][tid] = r.g;
+    };
+
+    store(fetch(k0), 0);
+    __syncthreads();
+
+    for (int64_t k = k0; k < k1; ++k) {
+        const int buf = int(k - k0) & 1;
+        const bool more = (k + 1 < k1);
+        Rec nxt{};
+        if (more)
+            nxt = fetch(k + 1);  // global loads in flight while this tile is swept
+
+        const double first = a.tile[3 * k + 0], last = a.tile[3 * k + 1];
+        const int cls = (last < t_lo) ? CAUSAL : ((first > t_hi) ? ANTI : MIXED);
+
+        // Terms are summed in FP32 over groups of GS = 8 sources and each
+        // group sum is folded into FP64.  Long FP32 running sums would round
+        // away every Gaussian-tail term below half an ulp of the sum, a
+        // systematic loss of ~1e-8 relative; groups of 8 keep it near 3e-10
+        // and equal across the six sums (the gradient combines them with
+        // heavy cancellation, so their errors must match).  Background sums go
+        // straight into the accumulators; the CAUSAL triggering sums keep FP64
+        // tile partials that take the target's time factor at the tile end.
+        double gt[KT][3];
+#pragma unroll
+        for (int q = 0; q < KT; ++q)
+            gt[q][0] = gt[q][1] = gt[q][2] = 0.0;
+
+        const double *sx = lx[buf];
+        const double *sy = ly[buf];
+        const double *st = lt[buf];
+
+        if (cls != MIXED) {
+            const bool causal = (cls == CAUSAL);
+            const float *srh = lrh[buf], *srl = lrl[buf], *svh = lvh[buf], *svl = lvl[buf], *sd = ld[buf];
+            for (int m0 = 0; m0 < TS; m0 += GS) {
+                float f[KT][6];
+#pragma unroll
+                for (int q = 0; q < KT; ++q)
+#pragma unroll
+                    for (int z = 0; z < 6; ++z)
+                        f[q][z] = 0.0f;
+                if (causal) {
+#pragma unroll
+                    for (int j = 0; j < GS; ++j) {
+                        const int m = m0 + j;
+                        const double xm = sx[m], ym = sy[m], tm = st[m];
+                        const float rhm = srh[m], rlm = srl[m], vhm = svh[m], vlm = svl[m], dm = sd[m];
+#pragma unroll
+                        for (int q = 0; q < KT; ++q) {
+                            const double dx = xn[q] - xm, dy = yn[q] - ym, dt = tsn[q] - tm;
+                            const double d2 = fma(dy, dy, dx * dx);
+                            const float D = float(d2);
+                            const float A = float(fma(dt, dt, d2));
+                            const float b = __builtin_amdgcn_exp2f(-A);
+                            const float t1 = fmaf(rlm, D, rhm * D);
+                            const float E = __builtin_amdgcn_exp2f(-t1);
+                            const float p = fmaf(vlm, E, vhm * E);
+                            f[q][0] += b;
+                            f[q][3] += p;
+                            if (GRAD) {
+                                f[q][1] = fmaf(b, D, f[q][1]);
+                                f[q][2] = fmaf(b, A, f[q][2]);
+                                f[q][4] = fmaf(p, t1, f[q][4]);
+                                f[q][5] = fmaf(p, dm, f[q][5]);
+                            }
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < GS; ++j) {
+                        const int m = m0 + j;
+                        const double xm = sx[m], ym = sy[m], tm = st[m];
+#pragma unroll
+                        for (int q = 0; q < KT; ++q) {
+                            const double dx = xn[q] - xm, dy = yn[q] - ym, dt = tsn[q] - tm;
+                            const double d2 = fma(dy, dy, dx * dx);
+                            const float A = float(fma(dt, dt, d2));
+                            const float b = __builtin_amdgcn_exp2f(-A);
+                            f[q][0] += b;
+                            if (GRAD) {
+                                const float D = float(d2);
+                                f[q][1] = fmaf(b, D, f[q][1]);
+                                f[q][2] = fmaf(b, A, f[q][2]);
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < KT; ++q) {
+                    acc[q][0] += double(f[q][0]);
+                    if (GRAD) {
+                        acc[q][1] += double(f[q][1]);
+                        acc[q][2] += double(f[q][2]);
+                    }
+                    if (causal) {
+                        gt[q][0] += double(f[q][3]);
+                        if (GRAD) {
+                            gt[q][1] += double(f[q][4]);
+                            gt[q][2] += double(f[q][5]);
+                        }
+                    }
+                }
+            }
+            if (causal) {
+#pragma unroll
+                for (int q = 0; q < KT; ++q) {
+                    const double dn = trn[q] - last;
+                    const double fn = exp(-a.omega * dn);
+                    acc[q][3] += fn * gt[q][0];
+                    if (GRAD) {
+                        acc[q][4] += fn * gt[q][1];
+                        acc[q][5] += fn * fma(dn, gt[q][0], gt[q][2]);
+                    }
+                }
+            }
+        } else {
+            // tiles overlapping the block's time range: per-pair tie-group
+            // masks and the triggering time factor formed per pair in FP64
+            const float *srh = lrh[buf], *srl = lrl[buf], *suh = luh[buf], *sul = lul[buf];
+            const int *sg = lg[buf];
+            for (int m0 = 0; m0 < TS; m0 += GS) {
+                float f[KT][6];
+#pragma unroll
+                for (int q = 0; q < KT; ++q)
+#pragma unroll
+                    for (int z = 0; z < 6; ++z)
+                        f[q][z] = 0.0f;
+                for (int j = 0; j < GS; ++j) {
+                    const int m = m0 + j;
+                    const double xm = sx[m], ym = sy[m], tm = st[m];
+                    const float rhm = srh[m], rlm = srl[m], uhm = suh[m], ulm = sul[m];
+                    const int gm = sg[m];
+#pragma unroll
+                    for (int q = 0; q < KT; ++q) {
+                        const double dx = xn[q] - xm, dy = yn[q] - ym, dt = tsn[q] - tm;
+                        const double d2 = fma(dy, dy, dx * dx);
+                        const float D = float(d2);
+                        const float A = float(fma(dt, dt, d2));
+                        float b = __builtin_amdgcn_exp2f(-A);
+                        b = (gm != gn[q]) ? b : 0.0f;
+                        const float t1 = fmaf(rlm, D, rhm * D);
+                        const float arg = float(fma(a.w2, dt, double(t1)));
+                        const float E = __builtin_amdgcn_exp2f(-arg);
+                        float p = fmaf(ulm, E, uhm * E);
+                        p = (gm < gn[q]) ? p : 0.0f;
+                        f[q][0] += b;
+                        f[q][3] += p;
+                        if (GRAD) {
+                            f[q][1] = fmaf(b, D, f[q][1]);
+                            f[q][2] = fmaf(b, A, f[q][2]);
+                            f[q][4] = fmaf(p, t1, f[q][4]);
+                            f[q][5] = fmaf(p, float(dt), f[q][5]);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < KT; ++q) {
+                    acc[q][0] += double(f[q][0]);
+                    acc[q][3] += double(f[q][3]);
+                    if (GRAD) {
+                        acc[q][1] += double(f[q][1]);
+                        acc[q][2] += double(f[q][2]);
+                        acc[q][4] += double(f[q][4]);
+                        acc[q][5] += double(f[q][5]) * a.inv_st;
+                    }
+                }
+            }
+        }
+
+        if (more)
+            store(nxt, buf ^ 1);
+        __syncthreads();
+    }
+
+    // write this chunk's sums in the natural units of the six sums
+    const int64_t stride = a.rows_pad;
+    double *out = a.partials + chunk * 6 * stride;
+#pragma unroll
+    for (int q = 0; q < KT; ++q) {
+        const int64_t i = i0 + tid + q * WG;
+        if (i >= iend)
+            continue;
+        const int64_t rr = i - a.row_begin;
+        const double ce = a.out_exp;
+        out[0 * stride + rr] = acc[q][0] * ce;
+        out[3 * stride + rr] = acc[q][3] * ce;
+        if (GRAD) {
+            out[1 * stride + rr] = acc[q][1] * (a.out_s1 * ce);
+            out[2 * stride + rr] = (acc[q][2] - acc[q][1]) * (a.out_s2 * ce);
+            out[4 * stride + rr] = acc[q][4] * (a.out_g1 * ce);
+            out[5 * stride + rr] = acc[q][5] * ce;
+        }
+    }
+}
+
+struct PairF64 {
+    const double *t, *x, *y, *s;
+    const int *g;
+    const double *tile;
+    double *partials;
+    int64_t n, row_begin, row_end, rows_pad, num_tiles, chunk_tiles, num_chunks, num_tb;
+    double ax, at, qh, omega;  // 1/(2 tau_x^2), 1/(2 tau_t^2), 1/(2 h0^2), omega
+};
+
+// The FP64 sweep: every pair term in FP64 with the direct formulas.
+template <bool GRAD>
+__global__ __launch_bounds__(WG) void k_pair_f64(PairF64 a)
+{
+    __shared__ double lx[2][TS], ly[2][TS], lt[2][TS], lu[2][TS];
+    __shared__ int lg[2][TS];
+
+    const int tid = threadIdx.x;
+    const int64_t tbr = blockIdx.x / a.num_chunks;
+    const int64_t chunk = blockIdx.x - tbr * a.num_chunks;
+    const int64_t tb = a.num_tb - 1 - tbr;
+    const int64_t i0 = a.row_begin + tb * TB;
+    const int64_t iend = (i0 + TB < a.row_end) ? i0 + TB : a.row_end;
+    const double t_lo = a.t[i0], t_hi = a.t[iend - 1];
+
+    double xn[KT], yn[KT], tn[KT];
+    int gn[KT];
+#pragma unroll
+    for (int q = 0; q < KT; ++q) {
+        int64_t i = i0 + tid + q * WG;
+        if (i >= iend)
+            i = iend - 1;
+        xn[q] = a.x[i];
+        yn[q] = a.y[i];
+        tn[q] = a.t[i];
+        gn[q] = a.g[i];
+    }
+    double acc[KT][6];
+#pragma unroll
+    for (int q = 0; q < KT; ++q)
+#pragma unroll
+        for (int z = 0; z < 6; ++z)
+            acc[q][z] = 0.0;
+
+    const int64_t k0 = chunk * a.chunk_tiles;
+    const int64_t k1 = (k0 + a.chunk_tiles < a.num_tiles) ? k0 + a.chunk_tiles : a.num_tiles;
+
+    auto fetch = [&](int64_t j, double &fx, double &fy, double &ft, double &fu, int &fg) {
+        if (j < a.n) {
+            fx = a.x[j];
+            fy = a.y[j];
+            ft = a.t[j];
+            const double sj = a.s[j];
+            fu = 1.0 / (sj * sj);
+            fg = a.g[j];
+        } else {
+            fx = PAD_COORD;
+            fy = PAD_COORD;
+            ft = 0.0;
+            fu = 0.0;
+            fg = INT_MAX;
+        }
+    };
+    {
+        double fx, fy, ft, fu;
+        int fg;
+        fetch(k0 * TS + tid, fx, fy, ft, fu, fg);
+        lx[0][tid] = fx;
+        ly[0][tid] = fy;
+        lt[0][tid] = ft;
+        lu[0][tid] = fu;
+        lg[0][tid] = fg;
+    }
+    __syncthreads();
+
+    for (int64_t k = k0; k < k1; ++k) {
+        const int buf = int(k - k0) & 1;
+        const bool more = (k + 1 < k1);
+        double px = 0, py = 0, pt = 0, pu = 0;
+        int pg = 0;
+        if (more)
+            fetch((k + 1) * TS + tid, px, py, pt, pu, pg);
+
+        const double first = a.tile[3 * k + 0], last = a.tile[3 * k + 1];
+        const int cls = (last < t_lo) ? CAUSAL : ((first > t_hi) ? ANTI : MIXED);
+        const int mlen = (k * TS + TS <= a.n) ? TS : int(a.n - k * TS);
+
+        for (int m = 0; m < mlen; ++m) {
+            const double xm = lx[buf][m], ym = ly[buf][m], tm = lt[buf][m], um = lu[buf][m];
+            const int gm = lg[buf][m];
+#pragma unroll
+            for (int q = 0; q < KT; ++q) {
+                const double dx = xn[q] - xm, dy = yn[q] - ym;
+                const double d2 = dx * dx + dy * dy;
+                const double dt = tn[q] - tm;
+                const bool use_b = (cls != MIXED) || (gm != gn[q]);
+                const bool use_g = (cls == CAUSAL) || (cls == MIXED && gm < gn[q]);
+                if (use_b) {
+                    const double b = exp(-(a.ax * d2 + a.at * dt * dt));
+                    acc[q][0] += b;
+                    if (GRAD) {
+                        acc[q][1] += b * d2;
+                        acc[q][2] += b * dt * dt;
+                    }
+                }
+                if (use_g) {
+                    const double e = um * exp(-(um * a.qh * d2 + a.omega * dt));
+                    acc[q][3] += e;
+                    if (GRAD) {
+                        acc[q][4] += e * (um * d2);
+                        acc[q][5] += e * dt;
+                    }
+                }
+            }
+        }
+        if (more) {
+            const int nb = buf ^ 1;
+            lx[nb][tid] = px;
+            ly[nb][tid] = py;
+            lt[nb][tid] = pt;
+            lu[nb][tid] = pu;
+            lg[nb][tid] = pg;
+        }
+        __syncthreads();
+    }
+
+    const int64_t stride = a.rows_pad;
+    double *out = a.partials + chunk * 6 * stride;
+#pragma unroll
+    for (int q = 0; q < KT; ++q) {
+        const int64_t i = i0 + tid + q * WG;
+        if (i >= iend)
+            continue;
+        const int64_t rr = i - a.row_begin;
+        out[0 * stride + rr] = acc[q][0];
+        out[3 * stride + rr] = acc[q][3];
+        if (GRAD) {
+            out[1 * stride + rr] = acc[q][1];
+            out[2 * stride + rr] = acc[q][2];
+            out[4 * stride + rr] = acc[q][4];
+            out[5 * stride + rr] = acc[q][5];
+        }
+    }
+}
+
+struct Fin {
+    const double *t, *x, *y, *s;   // raw events (the rescue sweep reads them)
+    const int *g;                  // tie-group ids
+    const double *partials;
+    int *status;                   // [0] flags, [1] rescue count
+    int *rescue;                   // rescue list of row offsets
+    double *rowvals;               // [7][rows_cap] per-row l_n and gradient terms
+    double *lam_out, *comp_out;
+    int64_t n, row_begin, rows, rows_pad, rows_cap, num_chunks;
+    double mu, tau_x, tau_t, xi, h0, omega, c_b, c_g;
+    double ax, at, qh;             // 1/(2 tau_x^2), 1/(2 tau_t^2), 1/(2 h0^2)
+    double rescue_lambda;          // FP32 rows with lambda below this are recomputed (0: never)
+};
+
+__device__ inline double std_normal_cdf(double z) { return 0.5 * erfc(-z * 0.70710678118654752440); }
+__device__ inline double std_normal_pdf(double z) { return 0.39894228040143267794 * exp(-0.5 * z * z); }
+
+// From the six pair sums of row i (natural units): l_n, its six gradient
+// terms, lambda_n and Lambda_n, all FP64.
+template <bool GRAD>
+__device__ void row_terms(const Fin &f, const double S[6], double ti, double tN, double v[7], double &lam,
+                          double &comp)
+{
+    const double B = f.c_b * S[0];
+    const double T = f.c_g * S[3];
+    lam = f.mu * B + f.xi * T;
+    const bool floored = !(lam >= LAMBDA_FLOOR);
+    const double av = tN - ti;
+    const double bg = std_normal_cdf(av / f.tau_t) - std_normal_cdf(-ti / f.tau_t);
+    const double ea = exp(-f.omega * av);
+    comp = f.mu * bg + f.xi * (1.0 - ea);
+    v[0] = log(floored ? LAMBDA_FLOOR : lam) - comp;
+    if (GRAD) {
+        const double tx = f.tau_x, tt = f.tau_t, h0 = f.h0, om = f.omega;
+        double dl[6] = {0, 0, 0, 0, 0, 0};
+        if (!floored) {
+            const double il = 1.0 / lam;
+            dl[0] = B * il;
+            dl[1] = f.mu * f.c_b * (S[1] / (tx * tx * tx) - 2.0 * S[0] / tx) * il;
+            dl[2] = f.mu * f.c_b * (S[2] / (tt * tt * tt) - S[0] / tt) * il;
+            dl[3] = T * il;
+            dl[4] = f.xi * f.c_g * (S[4] / (h0 * h0 * h0) - 2.0 * S[3] / h0) * il;
+            dl[5] = f.xi * f.c_g * (S[3] / om - S[5]) * il;
+        }
+        const double dcomp_taut = -(f.mu / (tt * tt)) * (av * std_normal_pdf(av / tt) + ti * std_normal_pdf(ti / tt));
+        v[1] = dl[0] - bg;
+        v[2] = dl[1];
+        v[3] = dl[2] - dcomp_taut;
+        v[4] = dl[3] - (1.0 - ea);
+        v[5] = dl[4];
+        v[6] = dl[5] - f.xi * av * ea;
+    }
+}
+
+// Per-row FP64 finalize: sums the chunk partials in a fixed order, then
+// lambda_n, the floored log, gradient terms and the compensator.
+template <bool GRAD>
+__global__ __launch_bounds__(256) void k_finalize(Fin f)
+{
+    const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (r >= f.rows)
+        return;
+    double S[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t c = 0; c < f.num_chunks; ++c) {
+        const double *p = f.partials + c * 6 * f.rows_pad + r;
+        S[0] += p[0];
+        S[3] += p[3 * f.rows_pad];
+        if (GRAD) {
+            S[1] += p[1 * f.rows_pad];
+            S[2] += p[2 * f.rows_pad];
+            S[4] += p[4 * f.rows_pad];
+            S[5] += p[5 * f.rows_pad];
+        }
+    }
+    const int64_t i = f.row_begin + r;
+    double v[7] = {0, 0, 0, 0, 0, 0, 0}, lam, comp;
+    row_terms<GRAD>(f, S, f.t[i], f.t[f.n - 1], v, lam, comp);
+    if (lam < f.rescue_lambda) {
+        const int slot = atomicAdd(&f.status[1], 1);
+        f.rescue[slot] = int(r);
+    }
+    const int nv = GRAD ? 7 : 1;
+    for (int z = 0; z < nv; ++z)
+        f.rowvals[z * f.rows_cap + r] = v[z];
+    if (f.lam_out)
+        f.lam_out[r] = lam;
+    if (f.comp_out)
+        f.comp_out[r] = comp;
+}
+
+// FP64 rescue: rows whose FP32 rate is underflow-limited are swept again
+// with every pair in FP64 (one workgroup per row, lanes strided over
+// sources), and their row values are replaced.  Workgroups stride over the
+// rescue list, so the grid size is independent of its length.
+template <bool GRAD>
+__global__ __launch_bounds__(256) void k_rescue(Fin f)
+{
+    __shared__ double red[6][256];
+    const int tid = threadIdx.x;
+    const int count = f.status[1];
+    for (int w = blockIdx.x; w < count; w += gridDim.x) {
+        const int64_t r = f.rescue[w];
+        const int64_t i = f.row_begin + r;
+        const double xn = f.x[i], yn = f.y[i], tn = f.t[i];
+        const int gn = f.g[i];
+        double S[6] = {0, 0, 0, 0, 0, 0};
+        for (int64_t m = tid; m < f.n; m += 256) {
+            const int gm = f.g[m];
+            if (gm == gn)
+                continue;
+            const double dx = xn - f.x[m], dy = yn - f.y[m];
+            const double d2 = dx * dx + dy * dy;
+            const double dt = tn - f.t[m];
+            const double b = exp(-(f.ax * d2 + f.at * dt * dt));
+            S[0] += b;
+            S[1] += b * d2;
+            S[2] += b * dt * dt;
+            if (gm < gn) {
+                const double sm = f.s[m];
+                const double um = 1.0 / (sm * sm);
+                const double e = um * exp(-(um * f.qh * d2 + f.omega * dt));
+                S[3] += e;
+                S[4] += e * (um * d2);
+                S[5] += e * dt;
+            }
+        }
+        for (int z = 0; z < 6; ++z)
+            red[z][tid] = S[z];
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (tid < h)
+                for (int z = 0; z < 6; ++z)
+                    red[z][tid] += red[z][tid + h];
+            __syncthreads();
+        }
+        if (tid == 0) {
+            double T6[6], v[7] = {0, 0, 0, 0, 0, 0, 0}, lam, comp;
+            for (int z = 0; z < 6; ++z)
+                T6[z] = red[z][0];
+            row_terms<GRAD>(f, T6, tn, f.t[f.n - 1], v, lam, comp);
+            const int nv = GRAD ? 7 : 1;
+            for (int z = 0; z < nv; ++z)
+                f.rowvals[z * f.rows_cap + r] = v[z];
+            if (f.lam_out)
+                f.lam_out[r] = lam;
+        }
+        __syncthreads();
+    }
+}
+
+// Fixed-order block sums of the row values.
+template <bool GRAD>
+__global__ __launch_bounds__(256) void k_blocksum(const double *__restrict__ rowvals, int64_t rows, int64_t rows_cap,
+                                                  double *__restrict__ blocks)
+{
+    __shared__ double red[7][256];
+    const int tid = threadIdx.x;
+    const int64_t r = int64_t(blockIdx.x) * 256 + tid;
+    const int nv = GRAD ? 7 : 1;
+    for (int z = 0; z < nv; ++z)
+        red[z][tid] = (r < rows) ? rowvals[z * rows_cap + r] : 0.0;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w)
+            for (int z = 0; z < nv; ++z)
+                red[z][tid] += red[z][tid + w];
+        __syncthreads();
+    }
+    if (tid == 0)
+        for (int z = 0; z < nv; ++z)
+            blocks[blockIdx.x * 7 + z] = red[z][0];
+}
+
+template <bool GRAD>
+__global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ blocks, int64_t nblk, const int *status,
+                                                double *loglik, double *grad)
+{
+    __shared__ double red[7][256];
+    const int tid = threadIdx.x;
+    const int nv = GRAD ? 7 : 1;
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t b = tid; b < nblk; b += 256)
+        for (int z = 0; z < nv; ++z)
+            v[z] += blocks[b * 7 + z];
+    for (int z = 0; z < nv; ++z)
+        red[z][tid] = v[z];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w)
+            for (int z = 0; z < nv; ++z)
+                red[z][tid] += red[z][tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const bool bad = status[0] != 0;
+        const double nan = __builtin_nan("");
+        if (loglik)
+            loglik[0] = bad ? nan : red[0][0];
+        if (GRAD && grad)
+            for (int z = 0; z < 6; ++z)
+                grad[z] = bad ? nan : red[1 + z][0];
+    }
+}
+
+// Per-row outputs of hawkes_event_terms become NaN when the data checks failed.
+__global__ void k_poison_rows(const int *status, double *lam, double *comp, int64_t rows)
+{
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= rows || status[0] == 0)
+        return;
+    const double nan = __builtin_nan("");
+    if (lam)
+        lam[r] = nan;
+    if (comp)
+        comp[r] = nan;
+}
+
+// ------------------------------------------------------------ host side
+
+thread_local char g_errbuf[512];
+
+bool g_timing = false;
+hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+bool g_timing_recorded = false;
+
+int validate(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t rb, int64_t re, const void *ws,
+             size_t ws_bytes, Layout *L)
+{
+    if (!ev || !th) {
+        set_error("null events or theta");
+        return HAWKES_EINVAL;
+    }
+    if (ev->n < 1 || ev->n > MAX_N) {
+        set_error("n = %lld outside [1, %lld]", (long long)ev->n, (long long)MAX_N);
+        return HAWKES_EINVAL;
+    }
+    if (!ev->t || !ev->x || !ev->y || !ev->s) {
+        set_error("null event array");
+        return HAWKES_EINVAL;
+    }
+    if (precision != HAWKES_FP64 && precision != HAWKES_FP32) {
+        set_error("precision %d is neither HAWKES_FP64 nor HAWKES_FP32", precision);
+        return HAWKES_EINVAL;
+    }
+    const double p[6] = {th->mu, th->tau_x, th->tau_t, th->xi, th->h0, th->omega};
+    for (int k = 0; k < 6; ++k)
+        if (!(p[k] > 0.0) || !std::isfinite(p[k])) {
+            set_error("theta component %d = %g is not finite and positive", k, p[k]);
+            return HAWKES_EINVAL;
+        }
+    if (rb < 0 || re > ev->n || rb > re) {
+        set_error("row range [%lld, %lld) not within [0, %lld]", (long long)rb, (long long)re, (long long)ev->n);
+        return HAWKES_ERANGE;
+    }
+    *L = make_layout(ev->n, precision);
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0 || ws_bytes < L->total) {
+        set_error("workspace %p of %zu bytes; need %zu bytes, 256-byte aligned", ws, ws_bytes, L->total);
+        return HAWKES_EWORKSPACE;
+    }
+    return HAWKES_OK;
+}
+
+int record_event(hipEvent_t ev, hipStream_t stream)
+{
+    const hipError_t e = hipEventRecord(ev, stream);
+    return e == hipSuccess ? HAWKES_OK : hip_failure(e, "hipEventRecord");
+}
+
+template <typename T>
+T *at(void *ws, size_t off)
+{
+    return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+enum Mode { MODE_LOGLIK, MODE_GRAD, MODE_TERMS };
+
+int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t rb, int64_t re, void *ws,
+        size_t ws_bytes, double *d_loglik, double *d_grad, double *d_lam, double *d_comp, Mode mode, void *stream_)
+{
+    Layout L;
+    int rc = validate(ev, th, precision, rb, re, ws, ws_bytes, &L);
+    if (rc != HAWKES_OK)
+        return rc;
+    if (mode != MODE_TERMS && !d_loglik) {
+        set_error("null loglik output");
+        return HAWKES_EINVAL;
+    }
+    if (mode == MODE_GRAD && !d_grad) {
+        set_error("null gradient output");
+        return HAWKES_EINVAL;
+    }
+    hipStream_t stream = as_stream(stream_);
+    const bool grad = (mode == MODE_GRAD);
+    const int64_t n = ev->n;
+    int *status = at<int>(ws, L.status);
+    int *g = at<int>(ws, L.g);
+    double *tile = at<double>(ws, L.tile);
+
+    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, stream, status);
+    const unsigned stage_blocks = unsigned(ceil_div(L.n_pad, 256));
+    hipLaunchKernelGGL(k_stage_common, dim3(stage_blocks), dim3(256), 0, stream, ev->t, ev->x, ev->y, ev->s, n,
+                       L.n_pad, g, tile, status);
+    if ((rc = check_launch("stage_common")) != HAWKES_OK)
+        return rc;
+
+    const int64_t rows = re - rb;
+    if (rows == 0) {
+        if (mode != MODE_TERMS)
+            hipLaunchKernelGGL(k_zero_outputs, dim3(1), dim3(64), 0, stream, d_loglik, grad ? d_grad : nullptr);
+        return check_launch("zero_outputs");
+    }
+
+    const Plan P = make_plan(rows, L.num_tiles);
+    const double tau_x = th->tau_x, tau_t = th->tau_t, h0 = th->h0, omega = th->omega;
+    double *partials = at<double>(ws, L.partials);
+    const unsigned pair_blocks = unsigned(P.num_tb * P.num_chunks);
+
+    if (precision == HAWKES_FP32) {
+        StageF32 sc;
+        sc.sx = std::sqrt(LOG2E / (2.0 * tau_x * tau_x));
+        sc.st = std::sqrt(LOG2E / (2.0 * tau_t * tau_t));
+        sc.rr = (tau_x / h0) * (tau_x / h0);
+        sc.omega = omega;
+        double *xs = at<double>(ws, L.xs), *ys = at<double>(ws, L.ys), *tsd = at<double>(ws, L.tsd);
+        float *rh = at<float>(ws, L.rh), *rl = at<float>(ws, L.rl), *vh = at<float>(ws, L.vh);
+        float *vl = at<float>(ws, L.vl), *dl = at<float>(ws, L.dl), *uh = at<float>(ws, L.uh);
+        float *ul = at<float>(ws, L.ul);
+        hipLaunchKernelGGL(k_stage_f32, dim3(stage_blocks), dim3(256), 0, stream, ev->t, ev->x, ev->y, ev->s, n,
+                           L.n_pad, sc, tile, xs, ys, tsd, rh, rl, vh, vl, dl, uh, ul);
+        if ((rc = check_launch("stage_f32")) != HAWKES_OK)
+            return rc;
+        PairF32 a;
+        a.xs = xs;
+        a.ys = ys;
+        a.tsd = tsd;
+        a.t = ev->t;
+        a.rh = rh;
+        a.rl = rl;
+        a.vh = vh;
+        a.vl = vl;
+        a.dl = dl;
+        a.uh = uh;
+        a.ul = ul;
+        a.g = g;
+        a.tile = tile;
+        a.partials = partials;
+        a.row_begin = rb;
+        a.row_end = re;
+        a.rows_pad = P.rows_pad;
+        a.num_tiles = L.num_tiles;
+        a.chunk_tiles = P.chunk_tiles;
+        a.num_chunks = P.num_chunks;
+        a.num_tb = P.num_tb;
+        a.omega = omega;
+        a.inv_st = 1.0 / sc.st;
+        a.out_s1 = 1.0 / (sc.sx * sc.sx);        // D = d^2 sx^2
+        a.out_s2 = 1.0 / (sc.st * sc.st);        // dt' = dt st
+        a.out_g1 = 2.0 * h0 * h0 / LOG2E;        // t1 = u d^2 log2(e) / (2 h0^2)
+        a.w2 = omega * LOG2E / sc.st;
+        a.out_exp = 1.0 / (1.0 + EXP2_MEAN_REL_ERR);
+        if (g_timing && (rc = record_event(g_ev_start, stream)) != HAWKES_OK)
+            return rc;
+        if (grad)
+            hipLaunchKernelGGL(k_pair_f32<true>, dim3(pair_blocks), dim3(WG), 0, stream, a);
+        else
+            hipLaunchKernelGGL(k_pair_f32<false>, dim3(pair_blocks), dim3(WG), 0, stream, a);
+        if (g_timing) {
+            if ((rc = record_event(g_ev_stop, stream)) != HAWKES_OK)
+                return rc;
+            g_timing_recorded = true;
+        }
+        if ((rc = check_launch("pair_f32")) != HAWKES_OK)
+            return rc;
+    } else {
+        PairF64 a;
+        a.t = ev->t;
+        a.x = ev->x;
+        a.y = ev->y;
+        a.s = ev->s;
+        a.g = g;
+        a.tile = tile;
+        a.partials = partials;
+        a.n = n;
+        a.row_begin = rb;
+        a.row_end = re;
+        a.rows_pad = P.rows_pad;
+        a.num_tiles = L.num_tiles;
+        a.chunk_tiles = P.chunk_tiles;
+        a.num_chunks = P.num_chunks;
+        a.num_tb = P.num_tb;
+        a.ax = 1.0 / (2.0 * tau_x * tau_x);
+        a.at = 1.0 / (2.0 * tau_t * tau_t);
+        a.qh = 1.0 / (2.0 * h0 * h0);
+        a.omega = omega;
+        if (g_timing && (rc = record_event(g_ev_start, stream)) != HAWKES_OK)
+            return rc;
+        if (grad)
+            hipLaunchKernelGGL(k_pair_f64<true>, dim3(pair_blocks), dim3(WG), 0, stream, a);
+        else
+            hipLaunchKernelGGL(k_pair_f64<false>, dim3(pair_blocks), dim3(WG), 0, stream, a);
+        if (g_timing) {
+            if ((rc = record_event(g_ev_stop, stream)) != HAWKES_OK)
+                return rc;
+            g_timing_recorded = true;
+        }
+        if ((rc = check_launch("pair_f64")) != HAWKES_OK)
+            return rc;
+    }
+
+    Fin f;
+    f.t = ev->t;
+    f.x = ev->x;
+    f.y = ev->y;
+    f.s = ev->s;
+    f.g = g;
+    f.partials = partials;
+    f.status = status;
+    f.rescue = at<int>(ws, L.rescue);
+    f.rowvals = at<double>(ws, L.rowvals);
+    f.lam_out = d_lam;
+    f.comp_out = d_comp;
+    f.n = n;
+    f.row_begin = rb;
+    f.rows = rows;
+    f.rows_pad = P.rows_pad;
+    f.rows_cap = L.rows_cap;
+    f.num_chunks = P.num_chunks;
+    f.mu = th->mu;
+    f.tau_x = tau_x;
+    f.tau_t = tau_t;
+    f.xi = th->xi;
+    f.h0 = h0;
+    f.omega = omega;
+    f.c_b = 1.0 / (std::pow(2.0 * M_PI, 1.5) * tau_x * tau_x * tau_t);
+    f.c_g = omega / (2.0 * M_PI * h0 * h0);
+    f.ax = 1.0 / (2.0 * tau_x * tau_x);
+    f.at = 1.0 / (2.0 * tau_t * tau_t);
+    f.qh = 1.0 / (2.0 * h0 * h0);
+    // Each FP32 pair term below 2^-126 may be lost to underflow; n of them
+    // bound the loss by n 2^-126 (mu c_b + xi c_g).  Rows whose rate is not
+    // 1/RESCUE_REL times larger than that are recomputed in FP64.
+    f.rescue_lambda = (precision == HAWKES_FP32)
+                          ? double(n) * std::ldexp(1.0, -126) * (f.mu * f.c_b + f.xi * f.c_g) / RESCUE_REL
+                          : 0.0;
+    const int64_t nblk = ceil_div(rows, 256);
+    if (grad)
+        hipLaunchKernelGGL(k_finalize<true>, dim3(unsigned(nblk)), dim3(256), 0, stream, f);
+    else
+        hipLaunchKernelGGL(k_finalize<false>, dim3(unsigned(nblk)), dim3(256), 0, stream, f);
+    if ((rc = check_launch("finalize")) != HAWKES_OK)
+        return rc;
+    if (precision == HAWKES_FP32) {
+        const unsigned rescue_wgs = unsigned(nblk < 256 ? nblk : 256);
+        if (grad)
+            hipLaunchKernelGGL(k_rescue<true>, dim3(rescue_wgs), dim3(256), 0, stream, f);
+        else
+            hipLaunchKernelGGL(k_rescue<false>, dim3(rescue_wgs), dim3(256), 0, stream, f);
+        if ((rc = check_launch("rescue")) != HAWKES_OK)
+            return rc;
+    }
+    if (mode == MODE_TERMS) {
+        hipLaunchKernelGGL(k_poison_rows, dim3(unsigned(nblk)), dim3(256), 0, stream, status, d_lam, d_comp, rows);
+        return check_launch("poison_rows");
+    }
+    double *blocks = at<double>(ws, L.blocks);
+    if (grad)
+        hipLaunchKernelGGL(k_blocksum<true>, dim3(unsigned(nblk)), dim3(256), 0, stream, f.rowvals, rows, L.rows_cap,
+                           blocks);
+    else
+        hipLaunchKernelGGL(k_blocksum<false>, dim3(unsigned(nblk)), dim3(256), 0, stream, f.rowvals, rows,
+                           L.rows_cap, blocks);
+    if ((rc = check_launch("blocksum")) != HAWKES_OK)
+        return rc;
+    if (grad)
+        hipLaunchKernelGGL(k_reduce<true>, dim3(1), dim3(256), 0, stream, blocks, nblk, status, d_loglik, d_grad);
+    else
+        hipLaunchKernelGGL(k_reduce<false>, dim3(1), dim3(256), 0, stream, blocks, nblk, status, d_loglik, nullptr);
+    return check_launch("reduce");
+}
+
+}  // namespace
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_errbuf, sizeof(g_errbuf), fmt, ap);
+    va_end(ap);
+}
+
+int hip_failure(hipError_t e, const char *what)
+{
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return HAWKES_EHIP;
+}
+
+int check_launch(const char *what)
+{
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? HAWKES_OK : hip_failure(e, what);
+}
+
+}  // namespace hawkes
+
+// ------------------------------------------------------------------ C ABI
+
+using namespace hawkes;
+
+extern "C" size_t hawkes_workspace_bytes(int64_t n, int precision)
+{
+    if (n < 1 || n > MAX_N || (precision != HAWKES_FP64 && precision != HAWKES_FP32))
+        return 0;
+    return make_layout(n, precision).total;
+}
+
+extern "C" int hawkes_loglik(const hawkes_events *events, const hawkes_theta *theta, int precision,
+                             int64_t row_begin, int64_t row_end, void *ws, size_t ws_bytes, double *d_loglik,
+                             void *stream)
+{
+    return run(events, theta, precision, row_begin, row_end, ws, ws_bytes, d_loglik, nullptr, nullptr, nullptr,
+               MODE_LOGLIK, stream);
+}
+
+extern "C" int hawkes_loglik_grad(const hawkes_events *events, const hawkes_theta *theta, int precision,
+                                  int64_t row_begin, int64_t row_end, void *ws, size_t ws_bytes, double *d_loglik,
+                                  double *d_grad, void *stream)
+{
+    return run(events, theta, precision, row_begin, row_end, ws, ws_bytes, d_loglik, d_grad, nullptr, nullptr,
+               MODE_GRAD, stream);
+}
+
+extern "C" int hawkes_event_terms(const hawkes_events *events, const hawkes_theta *theta, int precision,
+                                  int64_t row_begin, int64_t row_end, void *ws, size_t ws_bytes, double *d_lambda,
+                                  double *d_comp, void *stream)
+{
+    return run(events, theta, precision, row_begin, row_end, ws, ws_bytes, nullptr, nullptr, d_lambda, d_comp,
+               MODE_TERMS, stream);
+}
+
+extern "C" int hawkes_workspace_status(const void *ws, int *status, void *stream)
+{
+    if (!ws || !status) {
+        set_error("null workspace or status pointer");
+        return HAWKES_EINVAL;
+    }
+    int word = 0;
+    hipError_t e = hipStreamSynchronize(as_stream(stream));
+    if (e != hipSuccess)
+        return hip_failure(e, "hipStreamSynchronize");
+    e = hipMemcpy(&word, ws, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return hip_failure(e, "hipMemcpy(status)");
+    *status = (word & STATUS_DATA) ? HAWKES_EDATA : ((word & STATUS_ORDER) ? HAWKES_EORDER : HAWKES_OK);
+    return HAWKES_OK;
+}
+
+extern "C" int hawkes_set_timing(int enable)
+{
+    if (enable && !g_ev_start) {
+        hipError_t e = hipEventCreate(&g_ev_start);
+        if (e == hipSuccess)
+            e = hipEventCreate(&g_ev_stop);
+        if (e != hipSuccess)
+            return hip_failure(e, "hipEventCreate");
+    }
+    g_timing = enable != 0;
+    g_timing_recorded = false;
+    return HAWKES_OK;
+}
+
+extern "C" int hawkes_last_pair_kernel_ms(float *ms)
+{
+    if (!ms) {
+        set_error("null output pointer");
+        return HAWKES_EINVAL;
+    }
+    if (!g_timing_recorded) {
+        set_error("no timed pair kernel since timing was enabled");
+        return HAWKES_EINVAL;
+    }
+    hipError_t e = hipEventSynchronize(g_ev_stop);
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(ms, g_ev_start, g_ev_stop);
+    return e == hipSuccess ? HAWKES_OK : hip_failure(e, "hipEventElapsedTime");
+}
+
+extern "C" const char *hawkes_strerror(int status)
+{
+    switch (status) {
+    case HAWKES_OK: return "ok";
+    case HAWKES_EINVAL: return "invalid argument";
+    case HAWKES_ERANGE: return "row range out of bounds";
+    case HAWKES_EWORKSPACE: return "workspace missing, misaligned or too small";
+    case HAWKES_EHIP: return "HIP runtime error";
+    case HAWKES_EORDER: return "event times are not sorted";
+    case HAWKES_EDATA: return "non-finite event data or non-positive bandwidth scale";
+    default: return "unknown status";
+    }
+}
+
+extern "C" const char *hawkes_last_error(void) { return g_errbuf; }
+
+// Tuning hook (not part of the public header): workgroups the pair sweep aims
+// for per call; bounded by the workspace sizing.
+extern "C" int hawkes_tune_target_workgroups(int64_t wgs)
+{
+    if (wgs < 1 || wgs > MAX_TARGET_WGS)
+        return HAWKES_EINVAL;
+    g_target_wgs = wgs;
+    return HAWKES_OK;
+}

@@ -1,0 +1,183 @@
+"""Python face of libhawkes: device event sets, workspaces, and the calls.
+
+All arithmetic happens in the HIP library; PyTorch supplies device memory and
+the current stream.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+
+
+def _dev_f64(a, device) -> torch.Tensor:
+    t = torch.as_tensor(a, dtype=torch.float64)
+    return t.to(device).contiguous()
+
+
+@dataclass
+class DeviceEvents:
+    """An event set resident in HBM (FP64 SoA: t, x, y, s)."""
+
+    t: torch.Tensor
+    x: torch.Tensor
+    y: torch.Tensor
+    s: torch.Tensor
+
+    @classmethod
+    def from_arrays(cls, t, x, y, s, device="cuda") -> "DeviceEvents":
+        return cls(_dev_f64(t, device), _dev_f64(x, device), _dev_f64(y, device), _dev_f64(s, device))
+
+    @property
+    def n(self) -> int:
+        return int(self.t.shape[0])
+
+    def struct(self) -> _lib.Events:
+        for a in (self.t, self.x, self.y, self.s):
+            if a.dtype != torch.float64 or not a.is_cuda or not a.is_contiguous() or a.shape[0] != self.n:
+                raise ValueError("event arrays must be contiguous float64 CUDA tensors of equal length")
+        return _lib.Events(self.n, _lib.ptr(self.t), _lib.ptr(self.x), _lib.ptr(self.y), _lib.ptr(self.s))
+
+
+def workspace_bytes(n: int, precision="fp32") -> int:
+    return int(_lib.load().hawkes_workspace_bytes(int(n), _lib.precision_code(precision)))
+
+
+class Workspace:
+    """Caller-owned device scratch for the likelihood calls (allocated once)."""
+
+    def __init__(self, n: int, precision="fp32", device="cuda"):
+        nbytes = workspace_bytes(n, precision)
+        if nbytes == 0:
+            raise ValueError(f"invalid workspace request n={n} precision={precision}")
+        self.nbytes = nbytes
+        # over-allocate so the base can be aligned to 256 bytes
+        self._buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self._buf.data_ptr()
+        self.offset = (-base) % 256
+        self.ptr = base + self.offset
+
+    def status(self, stream=None) -> int:
+        st = ctypes.c_int(0)
+        _lib.check(_lib.load().hawkes_workspace_status(self.ptr, ctypes.byref(st), _lib.stream_handle(stream)),
+                   "hawkes_workspace_status")
+        return int(st.value)
+
+
+_WS_CACHE: dict = {}
+
+
+def _workspace(events: DeviceEvents, precision, ws: Workspace | None) -> Workspace:
+    if ws is not None:
+        return ws
+    key = (events.n, _lib.precision_code(precision), events.t.device)
+    w = _WS_CACHE.get(key)
+    if w is None:
+        _WS_CACHE.clear()
+        w = Workspace(events.n, precision, events.t.device)
+        _WS_CACHE[key] = w
+    return w
+
+
+def _rows(events: DeviceEvents, rows):
+    if rows is None:
+        return 0, events.n
+    r0, r1 = rows
+    return int(r0), int(r1)
+
+
+def loglik(events: DeviceEvents, theta, precision="fp32", rows=None, ws=None, out=None, stream=None) -> torch.Tensor:
+    """Log-likelihood of rows [r0, r1) as a 1-element float64 device tensor (asynchronous)."""
+    lib = _lib.load()
+    w = _workspace(events, precision, ws)
+    r0, r1 = _rows(events, rows)
+    out = torch.empty(1, dtype=torch.float64, device=events.t.device) if out is None else out
+    ev = events.struct()
+    th = _lib.theta_struct(theta)
+    _lib.check(lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(th), _lib.precision_code(precision), r0, r1,
+                                 w.ptr, w.nbytes, _lib.ptr(out), _lib.stream_handle(stream)), "hawkes_loglik")
+    return out
+
+
+def loglik_grad(events: DeviceEvents, theta, precision="fp32", rows=None, ws=None, out=None, grad=None,
+                stream=None):
+    """(loglik (1,), gradient (6,)) float64 device tensors, gradient w.r.t. natural theta."""
+    lib = _lib.load()
+    w = _workspace(events, precision, ws)
+    r0, r1 = _rows(events, rows)
+    dev = events.t.device
+    out = torch.empty(1, dtype=torch.float64, device=dev) if out is None else out
+    grad = torch.empty(6, dtype=torch.float64, device=dev) if grad is None else grad
+    ev = events.struct()
+    th = _lib.theta_struct(theta)
+    _lib.check(lib.hawkes_loglik_grad(ctypes.byref(ev), ctypes.byref(th), _lib.precision_code(precision), r0, r1,
+                                      w.ptr, w.nbytes, _lib.ptr(out), _lib.ptr(grad), _lib.stream_handle(stream)),
+               "hawkes_loglik_grad")
+    return out, grad
+
+
+def event_terms(events: DeviceEvents, theta, precision="fp32", rows=None, ws=None, stream=None):
+    """(lambda_n, Lambda_n) for the rows, float64 device tensors."""
+    lib = _lib.load()
+    w = _workspace(events, precision, ws)
+    r0, r1 = _rows(events, rows)
+    dev = events.t.device
+    lam = torch.empty(r1 - r0, dtype=torch.float64, device=dev)
+    comp = torch.empty(r1 - r0, dtype=torch.float64, device=dev)
+    ev = events.struct()
+    th = _lib.theta_struct(theta)
+    _lib.check(lib.hawkes_event_terms(ctypes.byref(ev), ctypes.byref(th), _lib.precision_code(precision), r0, r1,
+                                      w.ptr, w.nbytes, _lib.ptr(lam), _lib.ptr(comp), _lib.stream_handle(stream)),
+               "hawkes_event_terms")
+    return lam, comp
+
+
+def resample_locations(county: torch.Tensor, rect: torch.Tensor, seed: int, iteration: int,
+                       x_out: torch.Tensor, y_out: torch.Tensor, stream=None) -> None:
+    """Uniform within-county redraw of every location into x_out, y_out (device, in place)."""
+    lib = _lib.load()
+    n = int(county.shape[0])
+    for a, dt in ((county, torch.int32), (rect, torch.float64), (x_out, torch.float64), (y_out, torch.float64)):
+        if a.dtype != dt or not a.is_cuda or not a.is_contiguous():
+            raise ValueError("resample arguments must be contiguous CUDA tensors of the documented dtypes")
+    if x_out.shape[0] != n or y_out.shape[0] != n or rect.dim() != 2 or rect.shape[1] != 4:
+        raise ValueError("shape mismatch in resample arguments")
+    _lib.check(lib.hawkes_resample_locations(n, _lib.ptr(county), _lib.ptr(rect), int(rect.shape[0]),
+                                             int(seed) & (2**64 - 1), int(iteration) & (2**64 - 1),
+                                             _lib.ptr(x_out), _lib.ptr(y_out), _lib.stream_handle(stream)),
+               "hawkes_resample_locations")
+
+
+def set_timing(enable: bool) -> None:
+    _lib.check(_lib.load().hawkes_set_timing(1 if enable else 0), "hawkes_set_timing")
+
+
+def last_pair_kernel_ms() -> float:
+    ms = ctypes.c_float(0.0)
+    _lib.check(_lib.load().hawkes_last_pair_kernel_ms(ctypes.byref(ms)), "hawkes_last_pair_kernel_ms")
+    return float(ms.value)
+
+
+class HawkesLoglik(torch.autograd.Function):
+    """l(theta) with a hand-written adjoint: forward runs the fused
+    forward+adjoint sweep and keeps the gradient; backward scales it."""
+
+    @staticmethod
+    def forward(ctx, theta: torch.Tensor, events: DeviceEvents, precision="fp32", rows=None, ws=None):
+        ll, g = loglik_grad(events, theta, precision=precision, rows=rows, ws=ws)
+        ctx.save_for_backward(g)
+        ctx.theta_device = theta.device
+        return ll.reshape(())
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (g,) = ctx.saved_tensors
+        return (grad_out.to(g.device) * g).to(ctx.theta_device), None, None, None, None
+
+
+def hawkes_loglik(theta: torch.Tensor, events: DeviceEvents, precision="fp32", rows=None, ws=None) -> torch.Tensor:
+    return HawkesLoglik.apply(theta, events, precision, rows, ws)

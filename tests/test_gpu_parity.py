@@ -1,0 +1,308 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle.
+
+Tolerances (from the precision scheme of the library):
+  FP64 sweep: log-likelihood within 1e-12 relative, gradient within 1e-10.
+  FP32 sweep: log-likelihood within 1e-9 relative, gradient within 1e-6 relative
+              per component; per-event rates within 5e-6 relative.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+import paper_2407_11349_amd as hk
+from paper_2407_11349_amd import _lib
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_values.json")
+TOL = {"fp64": (1e-12, 1e-10, 1e-12), "fp32": (1e-9, 1e-6, 5e-6)}
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _dev(ev):
+    return hk.DeviceEvents.from_arrays(ev.t, ev.x, ev.y, ev.s)
+
+
+def _gpu_ll_grad(dev, th, prec, rows=None):
+    ll, g = hk.loglik_grad(dev, th, precision=prec, rows=rows)
+    torch.cuda.synchronize()
+    return float(ll.item()), g.cpu().numpy()
+
+
+def _check(ll, g, ll_ref, g_ref, prec, what):
+    tl, tg, _ = TOL[prec]
+    rel_l = abs(ll - ll_ref) / max(abs(ll_ref), 1e-300)
+    rel_g = np.abs(g - g_ref) / np.maximum(np.abs(g_ref), 1e-300)
+    _say(f"{what} {prec}: loglik rel err {rel_l:.2e}, grad rel err max {rel_g.max():.2e}")
+    assert rel_l <= tl, (what, prec, ll, ll_ref)
+    assert rel_g.max() <= tg, (what, prec, g, g_ref)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_config0_loglik_and_grad(prec):
+    ev = synth.generate(0)
+    th = synth.theta_default()
+    ll_ref, g_ref = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th)
+    ll, g = _gpu_ll_grad(_dev(ev), th, prec)
+    _check(ll, g, ll_ref, g_ref, prec, "n2000")
+    # the forward-only call gives the same value
+    ll2 = hk.loglik(_dev(ev), th, precision=prec)
+    torch.cuda.synchronize()
+    assert abs(float(ll2.item()) - ll_ref) / abs(ll_ref) <= TOL[prec][0]
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 255, 256, 257, 1023, 1025, 2049, 5003])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_ragged_sizes_per_event(n, prec):
+    ev = synth.generate(0, n=n, seed=500 + n)
+    th = synth.theta_default()
+    ll_ref, g_ref, lam_ref, comp_ref, _ = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th, per_row=True)
+    dev = _dev(ev)
+    lam, comp = hk.event_terms(dev, th, precision=prec)
+    torch.cuda.synchronize()
+    lam, comp = lam.cpu().numpy(), comp.cpu().numpy()
+    tl, tg, tev = TOL[prec]
+    pos = lam_ref > 0
+    np.testing.assert_allclose(lam[pos], lam_ref[pos], rtol=tev)
+    assert np.all(lam[~pos] <= 1e-300)
+    np.testing.assert_allclose(comp, comp_ref, rtol=1e-13, atol=1e-13)
+    ll, g = _gpu_ll_grad(dev, th, prec)
+    # a few events carry random FP32 error (per-event rms ~1e-7) that does not average out yet;
+    # the systematic part is held to 1e-9 by the larger cases
+    rand = 5e-7 * math.sqrt(n) if prec == "fp32" else 1e-12 * n
+    assert abs(ll - ll_ref) <= tl * abs(ll_ref) + rand
+    scale = np.maximum(np.abs(g_ref), 1e-9 * n)
+    assert np.max(np.abs(g - g_ref) / scale) <= tg
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_time_ties(prec):
+    """Integer-day times: many exact ties, excluded from both sums."""
+    ev = synth.generate(0, n=3000, seed=42)
+    t = np.floor(ev.t)
+    th = synth.theta_default()
+    ll_ref, g_ref, lam_ref, _, _ = oracle.loglik(t, ev.x, ev.y, ev.s, th, per_row=True)
+    dev = hk.DeviceEvents.from_arrays(t, ev.x, ev.y, ev.s)
+    lam, _ = hk.event_terms(dev, th, precision=prec)
+    ll, g = _gpu_ll_grad(dev, th, prec)
+    rel = lam.cpu().numpy() / lam_ref - 1.0
+    _say(f"ties {prec} per-event lambda: mean rel {rel.mean():.3e} rms {np.sqrt((rel**2).mean()):.3e}")
+    np.testing.assert_allclose(lam.cpu().numpy(), lam_ref, rtol=TOL[prec][2])
+    _check(ll, g, ll_ref, g_ref, prec, "ties")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_row_ranges_add_up(prec):
+    """Row slices (the paper's per-GPU shares) sum to the full value; empty slices give 0."""
+    ev = synth.generate(0, n=4100, seed=9)
+    th = synth.theta_default()
+    dev = _dev(ev)
+    ll, g = _gpu_ll_grad(dev, th, prec)
+    cuts = [0, 1, 1000, 1025, 3333, 4099, 4100]
+    parts = [_gpu_ll_grad(dev, th, prec, rows=(a, b)) for a, b in zip(cuts[:-1], cuts[1:])]
+    # FP32 slices regroup pairs into different tile classes, so they agree to FP32 rounding noise
+    tl, tg, _ = TOL[prec]
+    assert sum(p[0] for p in parts) == pytest.approx(ll, rel=tl)
+    np.testing.assert_allclose(sum(p[1] for p in parts), g, rtol=tg)
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        ref, gref = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th, rows=(a, b))
+        got, gg = _gpu_ll_grad(dev, th, prec, rows=(a, b))
+        rand = 5e-7 * math.sqrt(b - a) if prec == "fp32" else 1e-12 * (b - a)  # per-event FP32 noise
+        assert abs(got - ref) <= TOL[prec][0] * abs(ref) + rand
+    e, ge = _gpu_ll_grad(dev, th, prec, rows=(17, 17))
+    assert e == 0.0 and not ge.any()
+
+
+def _golden(name):
+    if not os.path.exists(GOLDEN):
+        return None
+    return json.load(open(GOLDEN)).get(name)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_config1_full_against_stored_oracle(prec):
+    gold = _golden("n100k")
+    assert gold is not None, "tests/golden/oracle_values.json lacks n100k"
+    ev = synth.generate(1)
+    assert ev.n == gold["n"]
+    th = np.array(gold["theta"])
+    ll, g = _gpu_ll_grad(_dev(ev), th, prec)
+    _check(ll, g, gold["loglik"], np.array(gold["grad"]), prec, "n100k")
+
+
+def test_config1_sampled_rows_precision_audit():
+    """Per-event rates of 2000 random rows of the 1e5 workload (FP32) against the oracle;
+    reports the mean and rms relative error of lambda_n (the bias that the 1e-9 target
+    on the full log-likelihood depends on)."""
+    ev = synth.generate(1)
+    th = synth.theta_default()
+    dev = _dev(ev)
+    rng = np.random.default_rng(3)
+    starts = np.sort(rng.choice(ev.n - 8, 250, replace=False))
+    rel = []
+    for a in starts:
+        lam_ref, _, _ = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th, rows=(a, a + 8), per_row=True)[2:5]
+        lam, _ = hk.event_terms(dev, th, precision="fp32", rows=(int(a), int(a) + 8))
+        rel.append(lam.cpu().numpy() / lam_ref - 1.0)
+    rel = np.concatenate(rel)
+    _say(f"n100k fp32 per-event lambda: mean rel {rel.mean():.3e} rms {np.sqrt((rel**2).mean()):.3e} "
+         f"max {np.abs(rel).max():.3e}")
+    assert np.abs(rel).max() <= TOL["fp32"][2]
+
+
+def test_config2_sampled_rows_and_stability():
+    """1e6 events, 1200 days: per-event rates of sampled rows against the oracle,
+    a finite log-likelihood, and (when stored) the full value against the oracle."""
+    ev = synth.generate(2)
+    th = synth.theta_default()
+    dev = _dev(ev)
+    ll, g = _gpu_ll_grad(dev, th, "fp32")
+    assert math.isfinite(ll) and np.isfinite(g).all()
+    rng = np.random.default_rng(4)
+    rows = np.sort(rng.choice(ev.n - 4, 64, replace=False))
+    for a in rows:
+        a = int(a)
+        lam_ref = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th, rows=(a, a + 4), per_row=True)[2]
+        lam, _ = hk.event_terms(dev, th, precision="fp32", rows=(a, a + 4))
+        np.testing.assert_allclose(lam.cpu().numpy(), lam_ref, rtol=TOL["fp32"][2])
+    gold = _golden("n1m")
+    if gold is not None:
+        _check(ll, g, gold["loglik"], np.array(gold["grad"]), "fp32", "n1m")
+
+
+def test_resample_bitwise_equals_oracle():
+    ev = synth.generate(1)
+    county = torch.from_numpy(ev.county).cuda()
+    rect = torch.from_numpy(ev.rect).cuda()
+    x = torch.empty(ev.n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for it in (0, 1, 2**40 + 3):
+        hk.resample_locations(county, rect, 2002, it, x, y)
+        torch.cuda.synchronize()
+        xr, yr = oracle.resample(ev.county, ev.rect, 2002, it)
+        assert np.array_equal(x.cpu().numpy(), xr) and np.array_equal(y.cpu().numpy(), yr)
+    bad = county.clone()
+    bad[5] = 10**6
+    hk.resample_locations(bad, rect, 1, 1, x, y)
+    torch.cuda.synchronize()
+    assert math.isnan(float(x[5].item())) and not torch.isnan(x[6])
+
+
+def test_autograd_function_backward():
+    ev = synth.generate(0, n=1500, seed=5)
+    th = torch.tensor(synth.theta_default(), dtype=torch.float64, requires_grad=True)
+    dev = _dev(ev)
+    ll = hk.hawkes_loglik(th, dev, "fp32")
+    (3.0 * ll).backward()
+    _, g_ref = oracle.loglik(ev.t, ev.x, ev.y, ev.s, synth.theta_default())
+    np.testing.assert_allclose(th.grad.numpy(), 3.0 * g_ref, rtol=1e-6)
+    # chain rule to log-space parameters
+    z = torch.log(torch.tensor(synth.theta_default(), dtype=torch.float64)).requires_grad_(True)
+    hk.hawkes_loglik(torch.exp(z), dev, "fp64").backward()
+    np.testing.assert_allclose(z.grad.numpy(), synth.theta_default() * g_ref, rtol=1e-10)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_bitwise_determinism(prec):
+    ev = synth.generate(0, n=7000, seed=8)
+    th = synth.theta_default()
+    dev = _dev(ev)
+    a = _gpu_ll_grad(dev, th, prec)
+    b = _gpu_ll_grad(dev, th, prec)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
+
+
+def test_chunking_does_not_change_results_beyond_rounding():
+    ev = synth.generate(0, n=9000, seed=10)
+    th = synth.theta_default()
+    dev = _dev(ev)
+    lib = _lib.load()
+    vals = []
+    try:
+        for wgs in (1, 64, 4096, 16384):
+            assert lib.hawkes_tune_target_workgroups(wgs) == 0
+            vals.append(_gpu_ll_grad(dev, th, "fp32"))
+    finally:
+        lib.hawkes_tune_target_workgroups(4096)
+    for ll, g in vals[1:]:
+        assert ll == pytest.approx(vals[0][0], rel=1e-11)
+        np.testing.assert_allclose(g, vals[0][1], rtol=1e-8)
+
+
+def test_device_data_checks():
+    ev = synth.generate(0, n=600, seed=2)
+    th = synth.theta_default()
+    t = ev.t.copy()
+    t[100], t[101] = t[101], t[100]
+    for prec in ("fp32", "fp64"):
+        dev = hk.DeviceEvents.from_arrays(t, ev.x, ev.y, ev.s)
+        ws = hk.Workspace(dev.n, prec)
+        ll, g = hk.loglik_grad(dev, th, precision=prec, ws=ws)
+        assert ws.status() == _lib.HAWKES_EORDER
+        assert math.isnan(float(ll.item())) and torch.isnan(g).all()
+        s = ev.s.copy()
+        s[7] = 0.0
+        dev2 = hk.DeviceEvents.from_arrays(ev.t, ev.x, ev.y, s)
+        ll2 = hk.loglik(dev2, th, precision=prec, ws=ws)
+        assert ws.status() == _lib.HAWKES_EDATA and math.isnan(float(ll2.item()))
+        lam, _ = hk.event_terms(dev2, th, precision=prec, ws=ws)
+        assert torch.isnan(lam).all()
+        ok = hk.loglik(_dev(ev), th, precision=prec, ws=ws)
+        assert ws.status() == _lib.HAWKES_OK and math.isfinite(float(ok.item()))
+
+
+def test_pair_kernel_timing_hook():
+    ev = synth.generate(0, n=20000, seed=1)
+    dev = _dev(ev)
+    hk.set_timing(True)
+    try:
+        hk.loglik_grad(dev, synth.theta_default(), precision="fp32")
+        ms = hk.last_pair_kernel_ms()
+    finally:
+        hk.set_timing(False)
+    assert 0.0 < ms < 1000.0
+
+
+def test_fp32_rescue_of_underflow_limited_rows():
+    """Narrow kernels: event 1's only background term is ~2e-39 in FP32 units (below the
+    FP32 normal range) yet lambda_1 ~ 1e-36 is above the floor.  The FP32 path must detect the
+    row and recompute it in FP64."""
+    t = np.array([1.0, 1.5])
+    x = np.array([0.0, 0.438])
+    y = np.array([0.0, 0.0])
+    s = np.array([1.0, 1.0])
+    th = np.array([1.0, 0.05, 0.05, 1.0, 0.05, 1.0])
+    ll_ref, g_ref, lam_ref, _, _ = oracle.loglik(t, x, y, s, th, per_row=True)
+    assert 1e-40 < lam_ref[0] < 1e-30
+    dev = hk.DeviceEvents.from_arrays(t, x, y, s)
+    lam, _ = hk.event_terms(dev, th, precision="fp32")
+    lam = lam.cpu().numpy()
+    assert lam[0] == pytest.approx(lam_ref[0], rel=1e-10)  # the rescued row: FP64
+    assert lam[1] == pytest.approx(lam_ref[1], rel=TOL["fp32"][2])
+    ll, g = _gpu_ll_grad(dev, th, "fp32")
+    assert abs(ll - ll_ref) <= 5e-7  # row 1 carries FP32 per-event noise
+    np.testing.assert_allclose(g, g_ref, rtol=1e-6)
+
+
+@pytest.mark.parametrize("h0", [3.0, 1.7])
+def test_fp32_model1_shared_bandwidth(h0):
+    """The paper's model 1: every source has the same spatial sd (s = 1), so a rounding of
+    the per-source exponent scale would be shared by all triggering terms."""
+    ev = synth.generate(1, n=20000, seed=71)
+    s = np.ones(ev.n)
+    th = synth.theta_default()
+    th[4] = h0
+    ll_ref, g_ref = oracle.loglik(ev.t, ev.x, ev.y, s, th)
+    dev = hk.DeviceEvents.from_arrays(ev.t, ev.x, ev.y, s)
+    ll, g = _gpu_ll_grad(dev, th, "fp32")
+    _check(ll, g, ll_ref, g_ref, "fp32", f"model1 h0={h0}")

@@ -1,0 +1,89 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+header declares, sizes workspaces, and rejects bad arguments on the host
+before touching the GPU."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2407_11349_amd import _lib
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "hawkes.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hawkes_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 11
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_workspace_bytes(lib):
+    assert lib.hawkes_workspace_bytes(0, 1) == 0
+    assert lib.hawkes_workspace_bytes(10, 7) == 0
+    assert lib.hawkes_workspace_bytes(-5, 0) == 0
+    for prec in (0, 1):
+        a = lib.hawkes_workspace_bytes(1, prec)
+        b = lib.hawkes_workspace_bytes(100_000, prec)
+        c = lib.hawkes_workspace_bytes(1_000_000, prec)
+        assert 0 < a < b <= c
+        assert a % 256 == 0 and c % 256 == 0
+    # FP32 keeps extra staged source records
+    assert lib.hawkes_workspace_bytes(5000, 1) > lib.hawkes_workspace_bytes(5000, 0)
+
+
+def test_strerror_and_codes(lib):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert lib.hawkes_strerror(code)
+    assert lib.hawkes_strerror(-99) == b"unknown status"
+
+
+def _ev(n, p=0x100000):
+    return _lib.Events(n, p, p, p, p)
+
+
+def test_host_validation_paths(lib):
+    th = _lib.Theta(0.5, 10.0, 7.0, 0.3, 2.0, 0.2)
+    ev = _ev(1000)
+    ws_need = lib.hawkes_workspace_bytes(1000, 1)
+    fake = 0x200000  # never dereferenced: every call below fails host validation
+    assert lib.hawkes_loglik(None, ctypes.byref(th), 1, 0, 10, fake, ws_need, fake, None) == -1
+    assert lib.hawkes_loglik(ctypes.byref(_ev(0)), ctypes.byref(th), 1, 0, 0, fake, ws_need, fake, None) == -1
+    assert lib.hawkes_loglik(ctypes.byref(_ev(1000, 0)), ctypes.byref(th), 1, 0, 1, fake, ws_need, fake, None) == -1
+    assert lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(th), 3, 0, 10, fake, ws_need, fake, None) == -1
+    for k in range(6):
+        for bad in (0.0, -1.0, float("nan"), float("inf")):
+            vals = [0.5, 10.0, 7.0, 0.3, 2.0, 0.2]
+            vals[k] = bad
+            tb = _lib.Theta(*vals)
+            assert lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(tb), 1, 0, 10, fake, ws_need, fake, None) == -1
+    assert b"theta" in lib.hawkes_last_error()
+    for r0, r1 in ((-1, 5), (0, 1001), (7, 6)):
+        assert lib.hawkes_loglik_grad(ctypes.byref(ev), ctypes.byref(th), 1, r0, r1, fake, ws_need, fake, fake,
+                                      None) == -2
+    assert lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(th), 1, 0, 10, fake, ws_need - 256, fake, None) == -3
+    assert lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(th), 1, 0, 10, fake + 8, ws_need, fake, None) == -3
+    assert lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(th), 1, 0, 10, None, ws_need, fake, None) == -3
+    assert lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(th), 1, 0, 10, fake, ws_need, None, None) == -1
+    assert lib.hawkes_loglik_grad(ctypes.byref(ev), ctypes.byref(th), 1, 0, 10, fake, ws_need, fake, None,
+                                  None) == -1
+    assert lib.hawkes_resample_locations(10, None, fake, 3, 1, 2, fake, fake, None) == -1
+    assert lib.hawkes_resample_locations(10, fake, fake, 0, 1, 2, fake, fake, None) == -1
+    assert lib.hawkes_resample_locations(0, None, None, 3, 1, 2, None, None, None) == 0
+    assert lib.hawkes_tune_target_workgroups(0) == -1
+    assert lib.hawkes_tune_target_workgroups(10**6) == -1
+    assert lib.hawkes_last_pair_kernel_ms(None) == -1
