@@ -1,0 +1,77 @@
+/*
+ * hawkes_mlp.h -- C ABI of the surrogate network in libhawkes.so.
+ *
+ * A small network replaces the exact log-likelihood inside the leapfrog
+ * steps of Hamiltonian Monte Carlo; the exact GPU likelihood corrects its
+ * error in a delayed-acceptance step.  The network maps standardised
+ * log-parameters z (6 values) to a standardised log-likelihood:
+ *
+ *   6 -> 256 -> 256 -> 256 -> 1, GELU activations (GELU(x) = x Phi(x)),
+ *   h1 = W1 z + b1, a1 = gelu(h1), h2 = W2 a1 + b2, a2 = gelu(h2),
+ *   h3 = W3 a2 + b3, a3 = gelu(h3), f = w4 . a3 + b4.
+ *
+ * Parameters are one flat FP32 vector of HAWKES_MLP_PARAMS values in the order
+ * W1 (256 x 6, row-major, out x in), b1 (256), W2 (256 x 256), b2, W3
+ * (256 x 256), b3, w4 (256), b4 (1).  The library keeps them in a state
+ * buffer (FP32 master weights, Adam moments, BF16 working copies); every
+ * forward and backward product uses the BF16 weights with FP32 accumulation.
+ *
+ * Training minimises the value + gradient ("Sobolev") loss over a batch of B
+ * tuples (z_b, y_b, g_b):
+ *   L = (1/B) sum_b (f(z_b) - y_b)^2 + lambda_g |grad_z f(z_b) - g_b|^2.
+ *
+ * Conventions as in hawkes.h: device pointers, asynchronous on `stream`,
+ * 256-byte aligned state and workspace buffers owned by the caller, no
+ * allocation, HAWKES_OK or a negative status.  Calls that share a state or
+ * workspace buffer must not overlap.
+ */
+#ifndef HAWKES_MLP_H
+#define HAWKES_MLP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HAWKES_MLP_PARAMS 133633
+
+/* Bytes of the network state buffer. */
+size_t hawkes_mlp_state_bytes(void);
+
+/* Bytes of workspace hawkes_mlp_loss_grad needs for a batch of `batch`
+ * tuples (0 if batch < 1 or batch > 2^22). */
+size_t hawkes_mlp_workspace_bytes(int64_t batch);
+
+/* Initialise the state from FP32 parameters d_params[HAWKES_MLP_PARAMS]
+ * (device): master weights, zero Adam moments, BF16 working copies. */
+int hawkes_mlp_load(void *d_state, const float *d_params, void *stream);
+
+/* Copy the FP32 master parameters out to d_params[HAWKES_MLP_PARAMS]. */
+int hawkes_mlp_store(const void *d_state, float *d_params, void *stream);
+
+/* Value and input gradient for `batch` inputs: d_z[batch][6] ->
+ * d_f[batch], d_gz[batch][6] (d_gz may be NULL). */
+int hawkes_mlp_forward(const void *d_state, const float *d_z, int64_t batch, float *d_f, float *d_gz,
+                       void *stream);
+
+/* Sobolev loss of a batch (d_z[batch][6], d_y[batch], d_g[batch][6]) into
+ * d_loss[1], and its gradient with respect to the flat parameter vector into
+ * d_grad[HAWKES_MLP_PARAMS] (if d_grad is NULL, into the workspace).  The
+ * gradient is deterministic: per-sample terms are summed in index order. */
+int hawkes_mlp_loss_grad(const void *d_state, const float *d_z, const float *d_y, const float *d_g,
+                         int64_t batch, float lambda_g, void *ws, size_t ws_bytes, float *d_loss,
+                         float *d_grad, void *stream);
+
+/* One Adam update (Kingma and Ba 2015, bias-corrected; `step` counts from 1)
+ * of the FP32 master weights with gradient d_grad, then a refresh of the
+ * BF16 working copies (round to nearest, ties to even). */
+int hawkes_mlp_adam_step(void *d_state, const float *d_grad, int64_t step, float lr, float beta1, float beta2,
+                         float eps, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HAWKES_MLP_H */

@@ -10,7 +10,7 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libhawkes.so"
-SOURCES = ["hawkes_loglik.hip", "hawkes_resample.hip"]
+SOURCES = ["hawkes_loglik.hip", "hawkes_resample.hip", "hawkes_mlp.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -1,0 +1,546 @@
+// hawkes_mlp.hip -- the BF16 surrogate network of the log-likelihood on gfx950.
+//
+// Network 6 -> 256 -> 256 -> 256 -> 1 with GELU activations (x Phi(x)):
+//   h1 = W1 z + b1, a1 = gelu(h1), h2 = W2 a1 + b2, a2 = gelu(h2),
+//   h3 = W3 a2 + b3, a3 = gelu(h3), f = w4 . a3 + b4.
+// Flat parameter layout (133,633 values): W1 (256x6, out x in), b1, W2
+// (256x256), b2, W3 (256x256), b3, w4 (256), b4.
+//
+// The state buffer holds FP32 master weights, the two Adam moment vectors,
+// and BF16 working copies: the flat vector in its own layout plus W2 and W3
+// transposed (in x out), so that every matrix-vector product of the forward
+// and backward passes reads weights coalesced across the 256 lanes of a
+// workgroup.  All products accumulate in FP32.
+//
+// Training loss (value + gradient matching):
+//   L = (1/B) sum_b (f(z_b) - y_b)^2 + lambda |grad_z f(z_b) - g_b|^2.
+// Its parameter gradient uses d/dtheta [r . grad_z f] = d/dtheta [D_r f] for
+// r = grad_z f - g held fixed: per sample a primal pass, the reverse pass for
+// grad_z f, a forward tangent pass along r, and one reverse pass through the
+// primal and tangent computations; per-sample adjoint vectors are then
+// contracted over the batch in a fixed order (deterministic).
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "hawkes.h"
+#include "hawkes_common.h"
+#include "hawkes_mlp.h"
+
+namespace hawkes {
+namespace {
+
+constexpr int H = 256;
+constexpr int DZ = 6;
+constexpr int64_t P = HAWKES_MLP_PARAMS;
+// offsets of the parameter blocks in the flat vector
+constexpr int64_t OW1 = 0, OB1 = OW1 + H * DZ, OW2 = OB1 + H, OB2 = OW2 + H * H, OW3 = OB2 + H, OB3 = OW3 + H * H,
+                  OW4 = OB3 + H, OB4 = OW4 + H;
+static_assert(OB4 + 1 == P, "parameter layout");
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct StateLayout {
+    size_t master, m, v, wb, wt2, wt3, total;
+};
+
+StateLayout state_layout()
+{
+    StateLayout s;
+    size_t off = 0;
+    s.master = off;
+    off = align256(off + sizeof(float) * P);
+    s.m = off;
+    off = align256(off + sizeof(float) * P);
+    s.v = off;
+    off = align256(off + sizeof(float) * P);
+    s.wb = off;
+    off = align256(off + sizeof(uint16_t) * P);
+    s.wt2 = off;
+    off = align256(off + sizeof(uint16_t) * H * H);
+    s.wt3 = off;
+    off = align256(off + sizeof(uint16_t) * H * H);
+    s.total = off;
+    return s;
+}
+
+struct Net {
+    const uint16_t *w;    // flat BF16 copy
+    const uint16_t *wt2;  // W2 transposed: wt2[k * H + j] = W2[j][k]
+    const uint16_t *wt3;
+};
+
+Net net_of(const void *state)
+{
+    const StateLayout L = state_layout();
+    const char *b = static_cast<const char *>(state);
+    return Net{reinterpret_cast<const uint16_t *>(b + L.wb), reinterpret_cast<const uint16_t *>(b + L.wt2),
+               reinterpret_cast<const uint16_t *>(b + L.wt3)};
+}
+
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+// round to nearest, ties to even; NaN stays NaN
+__device__ inline uint16_t f32_to_bf16(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu))
+        return uint16_t((u >> 16) | 0x40u);
+    const uint32_t lsb = (u >> 16) & 1u;
+    return uint16_t((u + 0x7fffu + lsb) >> 16);
+}
+
+constexpr float K_SQRT1_2 = 0.70710678118654752440f;
+constexpr float K_INV_SQRT_2PI = 0.39894228040143267794f;
+
+__device__ inline float gelu(float x) { return 0.5f * x * (1.0f + erff(x * K_SQRT1_2)); }
+__device__ inline float gelu_d1(float x)
+{
+    return 0.5f * (1.0f + erff(x * K_SQRT1_2)) + x * K_INV_SQRT_2PI * expf(-0.5f * x * x);
+}
+__device__ inline float gelu_d2(float x) { return K_INV_SQRT_2PI * expf(-0.5f * x * x) * (2.0f - x * x); }
+
+// y_j = sum_k M[k * H + j] v[k]  (M stored k-major: coalesced over j)
+__device__ inline float matvec_kmajor(const uint16_t *__restrict__ M, const float *v, int j)
+{
+    float acc = 0.0f;
+#pragma unroll 8
+    for (int k = 0; k < H; ++k)
+        acc = fmaf(bf16_to_f32(M[k * H + j]), v[k], acc);
+    return acc;
+}
+
+// block-wide sum of one value per thread (256 threads), result in every thread
+__device__ inline float block_sum(float v, float *red)
+{
+    const int j = threadIdx.x;
+    red[j] = v;
+    __syncthreads();
+    for (int w = H / 2; w > 0; w >>= 1) {
+        if (j < w)
+            red[j] += red[j + w];
+        __syncthreads();
+    }
+    const float r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// Value and input gradient, one workgroup per sample.
+__global__ __launch_bounds__(H) void k_mlp_forward(Net net, const float *__restrict__ z, int64_t B,
+                                                   float *__restrict__ f_out, float *__restrict__ gz_out)
+{
+    __shared__ float sz[DZ], a1[H], a2[H], d[H], red[H];
+    const int j = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    if (j < DZ)
+        sz[j] = z[b * DZ + j];
+    __syncthreads();
+    const uint16_t *w = net.w;
+    float h1 = bf16_to_f32(w[OB1 + j]);
+#pragma unroll
+    for (int i = 0; i < DZ; ++i)
+        h1 = fmaf(bf16_to_f32(w[OW1 + j * DZ + i]), sz[i], h1);
+    a1[j] = gelu(h1);
+    const float s1 = gelu_d1(h1);
+    __syncthreads();
+    const float h2 = bf16_to_f32(w[OB2 + j]) + matvec_kmajor(net.wt2, a1, j);
+    a2[j] = gelu(h2);
+    const float s2 = gelu_d1(h2);
+    __syncthreads();
+    const float h3 = bf16_to_f32(w[OB3 + j]) + matvec_kmajor(net.wt3, a2, j);
+    const float w4 = bf16_to_f32(w[OW4 + j]);
+    const float f = block_sum(w4 * gelu(h3), red) + bf16_to_f32(w[OB4]);
+    d[j] = w4 * gelu_d1(h3);
+    __syncthreads();
+    const float d2 = s2 * matvec_kmajor(w + OW3, d, j);  // (W3^T d3)_j: W3 row-major is k-major for W3^T
+    __syncthreads();
+    d[j] = d2;
+    __syncthreads();
+    const float d1 = s1 * matvec_kmajor(w + OW2, d, j);
+    float g[DZ];
+#pragma unroll
+    for (int i = 0; i < DZ; ++i)
+        g[i] = block_sum(bf16_to_f32(w[OW1 + j * DZ + i]) * d1, red);
+    if (j == 0) {
+        f_out[b] = f;
+        if (gz_out)
+            for (int i = 0; i < DZ; ++i)
+                gz_out[b * DZ + i] = g[i];
+    }
+}
+
+// Per-sample vectors of the Sobolev-loss gradient (see file header), 12 x 256
+// floats per sample plus z, r (6 each), cf and the sample loss.
+struct TrainWs {
+    float *vec;     // [B][12][H]: h1b t1b | h2b t2b a1 u1 | h3b t3b a2 u2 | a3 u3
+    float *zr;      // [B][12]: z, r
+    float *cf;      // [B]
+    float *loss;    // [B]
+};
+constexpr int NV = 12;
+enum { V_H1B, V_T1B, V_H2B, V_T2B, V_A1, V_U1, V_H3B, V_T3B, V_A2, V_U2, V_A3, V_U3 };
+
+__global__ __launch_bounds__(H) void k_mlp_train_sample(Net net, const float *__restrict__ z,
+                                                        const float *__restrict__ y, const float *__restrict__ g,
+                                                        int64_t B, float lam, TrainWs ws)
+{
+    __shared__ float sz[DZ], sr[DZ], v1[H], v2[H], red[H];
+    const int j = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const uint16_t *w = net.w;
+    float *vec = ws.vec + b * NV * H;
+    if (j < DZ)
+        sz[j] = z[b * DZ + j];
+    __syncthreads();
+    // primal pass
+    float h1 = bf16_to_f32(w[OB1 + j]);
+#pragma unroll
+    for (int i = 0; i < DZ; ++i)
+        h1 = fmaf(bf16_to_f32(w[OW1 + j * DZ + i]), sz[i], h1);
+    const float a1 = gelu(h1), s1 = gelu_d1(h1);
+    v1[j] = a1;
+    __syncthreads();
+    const float h2 = bf16_to_f32(w[OB2 + j]) + matvec_kmajor(net.wt2, v1, j);
+    const float a2 = gelu(h2), s2 = gelu_d1(h2);
+    v2[j] = a2;
+    __syncthreads();
+    const float h3 = bf16_to_f32(w[OB3 + j]) + matvec_kmajor(net.wt3, v2, j);
+    const float a3 = gelu(h3), s3 = gelu_d1(h3);
+    const float w4 = bf16_to_f32(w[OW4 + j]);
+    const float f = block_sum(w4 * a3, red) + bf16_to_f32(w[OB4]);
+    // input gradient
+    v1[j] = w4 * s3;
+    __syncthreads();
+    const float d2 = s2 * matvec_kmajor(w + OW3, v1, j);
+    v2[j] = d2;
+    __syncthreads();
+    const float d1 = s1 * matvec_kmajor(w + OW2, v2, j);
+    float rr[DZ];
+#pragma unroll
+    for (int i = 0; i < DZ; ++i)
+        rr[i] = block_sum(bf16_to_f32(w[OW1 + j * DZ + i]) * d1, red) - g[b * DZ + i];
+    const float e = f - y[b];
+    if (j < DZ)
+        sr[j] = rr[j];
+    __syncthreads();
+    // tangent pass along r
+    float t1 = 0.0f;
+#pragma unroll
+    for (int i = 0; i < DZ; ++i)
+        t1 = fmaf(bf16_to_f32(w[OW1 + j * DZ + i]), sr[i], t1);
+    const float u1 = s1 * t1;
+    v1[j] = u1;
+    __syncthreads();
+    const float t2 = matvec_kmajor(net.wt2, v1, j);
+    const float u2 = s2 * t2;
+    __syncthreads();
+    v2[j] = u2;
+    __syncthreads();
+    const float t3 = matvec_kmajor(net.wt3, v2, j);
+    const float u3 = s3 * t3;
+    // reverse pass of J = cf f + ct D_r f
+    const float cf = 2.0f * e / float(B);
+    const float ct = 2.0f * lam / float(B);
+    const float a3b = cf * w4, u3b = ct * w4;
+    const float t3b = u3b * s3;
+    const float h3b = a3b * s3 + u3b * gelu_d2(h3) * t3;
+    __syncthreads();
+    v1[j] = h3b;
+    v2[j] = t3b;
+    __syncthreads();
+    const float a2b = matvec_kmajor(w + OW3, v1, j);
+    const float u2b = matvec_kmajor(w + OW3, v2, j);
+    const float t2b = u2b * s2;
+    const float h2b = a2b * s2 + u2b * gelu_d2(h2) * t2;
+    __syncthreads();
+    v1[j] = h2b;
+    v2[j] = t2b;
+    __syncthreads();
+    const float a1b = matvec_kmajor(w + OW2, v1, j);
+    const float u1b = matvec_kmajor(w + OW2, v2, j);
+    const float t1b = u1b * s1;
+    const float h1b = a1b * s1 + u1b * gelu_d2(h1) * t1;
+    vec[V_H1B * H + j] = h1b;
+    vec[V_T1B * H + j] = t1b;
+    vec[V_H2B * H + j] = h2b;
+    vec[V_T2B * H + j] = t2b;
+    vec[V_A1 * H + j] = a1;
+    vec[V_U1 * H + j] = u1;
+    vec[V_H3B * H + j] = h3b;
+    vec[V_T3B * H + j] = t3b;
+    vec[V_A2 * H + j] = a2;
+    vec[V_U2 * H + j] = u2;
+    vec[V_A3 * H + j] = a3;
+    vec[V_U3 * H + j] = u3;
+    if (j < DZ) {
+        ws.zr[b * 12 + j] = sz[j];
+        ws.zr[b * 12 + DZ + j] = sr[j];
+    }
+    if (j == 0) {
+        float rn = 0.0f;
+        for (int i = 0; i < DZ; ++i)
+            rn = fmaf(rr[i], rr[i], rn);
+        ws.cf[b] = cf;
+        ws.loss[b] = e * e + lam * rn;
+    }
+}
+
+// Parameter gradient: contractions of the per-sample vectors over the batch,
+// one thread per parameter, samples in index order.
+__global__ __launch_bounds__(256) void k_mlp_wgrad(TrainWs ws, int64_t B, float ct, float *__restrict__ grad)
+{
+    const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= P)
+        return;
+    float acc = 0.0f;
+    if (p < OB1) {  // W1[j][i]
+        const int jj = int(p / DZ), i = int(p % DZ);
+        for (int64_t b = 0; b < B; ++b) {
+            const float *vec = ws.vec + b * NV * H;
+            acc = fmaf(vec[V_H1B * H + jj], ws.zr[b * 12 + i], acc);
+            acc = fmaf(vec[V_T1B * H + jj], ws.zr[b * 12 + DZ + i], acc);
+        }
+    } else if (p < OW2) {
+        const int jj = int(p - OB1);
+        for (int64_t b = 0; b < B; ++b)
+            acc += ws.vec[b * NV * H + V_H1B * H + jj];
+    } else if (p < OB2) {  // W2[j][k]
+        const int jj = int((p - OW2) / H), k = int((p - OW2) % H);
+        for (int64_t b = 0; b < B; ++b) {
+            const float *vec = ws.vec + b * NV * H;
+            acc = fmaf(vec[V_H2B * H + jj], vec[V_A1 * H + k], acc);
+            acc = fmaf(vec[V_T2B * H + jj], vec[V_U1 * H + k], acc);
+        }
+    } else if (p < OW3) {
+        const int jj = int(p - OB2);
+        for (int64_t b = 0; b < B; ++b)
+            acc += ws.vec[b * NV * H + V_H2B * H + jj];
+    } else if (p < OB3) {  // W3[j][k]
+        const int jj = int((p - OW3) / H), k = int((p - OW3) % H);
+        for (int64_t b = 0; b < B; ++b) {
+            const float *vec = ws.vec + b * NV * H;
+            acc = fmaf(vec[V_H3B * H + jj], vec[V_A2 * H + k], acc);
+            acc = fmaf(vec[V_T3B * H + jj], vec[V_U2 * H + k], acc);
+        }
+    } else if (p < OW4) {
+        const int jj = int(p - OB3);
+        for (int64_t b = 0; b < B; ++b)
+            acc += ws.vec[b * NV * H + V_H3B * H + jj];
+    } else if (p < OB4) {  // w4[j]
+        const int jj = int(p - OW4);
+        for (int64_t b = 0; b < B; ++b) {
+            const float *vec = ws.vec + b * NV * H;
+            acc = fmaf(ws.cf[b], vec[V_A3 * H + jj], acc);
+            acc = fmaf(ct, vec[V_U3 * H + jj], acc);
+        }
+    } else {
+        for (int64_t b = 0; b < B; ++b)
+            acc += ws.cf[b];
+    }
+    grad[p] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_loss_reduce(const float *__restrict__ loss, int64_t B, float *out)
+{
+    __shared__ float red[256];
+    const int j = threadIdx.x;
+    float s = 0.0f;
+    for (int64_t b = j; b < B; b += 256)
+        s += loss[b];
+    red[j] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (j < w)
+            red[j] += red[j + w];
+        __syncthreads();
+    }
+    if (j == 0)
+        out[0] = red[0] / float(B);
+}
+
+// BF16 working copies (flat and transposed W2, W3) from the FP32 master.
+__global__ __launch_bounds__(256) void k_mlp_refresh(const float *__restrict__ master, uint16_t *__restrict__ wb,
+                                                     uint16_t *__restrict__ wt2, uint16_t *__restrict__ wt3)
+{
+    const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= P)
+        return;
+    const uint16_t h = f32_to_bf16(master[p]);
+    wb[p] = h;
+    if (p >= OW2 && p < OB2) {
+        const int64_t q = p - OW2;
+        wt2[(q % H) * H + q / H] = h;
+    } else if (p >= OW3 && p < OB3) {
+        const int64_t q = p - OW3;
+        wt3[(q % H) * H + q / H] = h;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_load(const float *__restrict__ src, float *__restrict__ master,
+                                                  float *__restrict__ m, float *__restrict__ v)
+{
+    const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= P)
+        return;
+    master[p] = src[p];
+    m[p] = 0.0f;
+    v[p] = 0.0f;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_copy(const float *__restrict__ src, float *__restrict__ dst)
+{
+    const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p < P)
+        dst[p] = src[p];
+}
+
+// Adam (Kingma and Ba, 2015) with bias correction on the FP32 master weights.
+__global__ __launch_bounds__(256) void k_mlp_adam(float *__restrict__ master, float *__restrict__ m,
+                                                  float *__restrict__ v, const float *__restrict__ grad, float lr,
+                                                  float beta1, float beta2, float eps, float c1, float c2)
+{
+    const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= P)
+        return;
+    const float gr = grad[p];
+    const float mm = beta1 * m[p] + (1.0f - beta1) * gr;
+    const float vv = beta2 * v[p] + (1.0f - beta2) * gr * gr;
+    m[p] = mm;
+    v[p] = vv;
+    master[p] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+struct TrainLayout {
+    size_t vec, zr, cf, loss, grad, total;
+};
+
+TrainLayout train_layout(int64_t B)
+{
+    TrainLayout t;
+    size_t off = 0;
+    t.vec = off;
+    off = align256(off + sizeof(float) * size_t(B) * NV * H);
+    t.zr = off;
+    off = align256(off + sizeof(float) * size_t(B) * 12);
+    t.cf = off;
+    off = align256(off + sizeof(float) * size_t(B));
+    t.loss = off;
+    off = align256(off + sizeof(float) * size_t(B));
+    t.grad = off;
+    off = align256(off + sizeof(float) * P);
+    t.total = off;
+    return t;
+}
+
+constexpr int64_t MAX_BATCH = int64_t(1) << 22;
+
+bool aligned256(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+
+}  // namespace
+}  // namespace hawkes
+
+using namespace hawkes;
+
+extern "C" size_t hawkes_mlp_state_bytes(void) { return state_layout().total; }
+
+extern "C" size_t hawkes_mlp_workspace_bytes(int64_t batch)
+{
+    if (batch < 1 || batch > MAX_BATCH)
+        return 0;
+    return train_layout(batch).total;
+}
+
+extern "C" int hawkes_mlp_load(void *d_state, const float *d_params, void *stream)
+{
+    if (!d_state || !d_params || !aligned256(d_state)) {
+        set_error("mlp_load: null or misaligned pointer");
+        return HAWKES_EINVAL;
+    }
+    const StateLayout L = state_layout();
+    char *s = static_cast<char *>(d_state);
+    const unsigned blocks = unsigned((P + 255) / 256);
+    hipStream_t st = as_stream(stream);
+    hipLaunchKernelGGL(k_mlp_load, dim3(blocks), dim3(256), 0, st, d_params, reinterpret_cast<float *>(s + L.master),
+                       reinterpret_cast<float *>(s + L.m), reinterpret_cast<float *>(s + L.v));
+    hipLaunchKernelGGL(k_mlp_refresh, dim3(blocks), dim3(256), 0, st, reinterpret_cast<const float *>(s + L.master),
+                       reinterpret_cast<uint16_t *>(s + L.wb), reinterpret_cast<uint16_t *>(s + L.wt2),
+                       reinterpret_cast<uint16_t *>(s + L.wt3));
+    return check_launch("mlp_load");
+}
+
+extern "C" int hawkes_mlp_store(const void *d_state, float *d_params, void *stream)
+{
+    if (!d_state || !d_params || !aligned256(d_state)) {
+        set_error("mlp_store: null or misaligned pointer");
+        return HAWKES_EINVAL;
+    }
+    const StateLayout L = state_layout();
+    hipLaunchKernelGGL(k_mlp_copy, dim3(unsigned((P + 255) / 256)), dim3(256), 0, as_stream(stream),
+                       reinterpret_cast<const float *>(static_cast<const char *>(d_state) + L.master), d_params);
+    return check_launch("mlp_store");
+}
+
+extern "C" int hawkes_mlp_forward(const void *d_state, const float *d_z, int64_t batch, float *d_f, float *d_gz,
+                                  void *stream)
+{
+    if (!d_state || !d_z || !d_f || !aligned256(d_state) || batch < 1 || batch > MAX_BATCH) {
+        set_error("mlp_forward: invalid arguments (batch %lld)", (long long)batch);
+        return HAWKES_EINVAL;
+    }
+    hipLaunchKernelGGL(k_mlp_forward, dim3(unsigned(batch)), dim3(H), 0, as_stream(stream), net_of(d_state), d_z,
+                       batch, d_f, d_gz);
+    return check_launch("mlp_forward");
+}
+
+extern "C" int hawkes_mlp_loss_grad(const void *d_state, const float *d_z, const float *d_y, const float *d_g,
+                                    int64_t batch, float lambda_g, void *ws, size_t ws_bytes, float *d_loss,
+                                    float *d_grad, void *stream)
+{
+    if (!d_state || !d_z || !d_y || !d_g || !d_loss || !aligned256(d_state) || batch < 1 || batch > MAX_BATCH ||
+        !(lambda_g >= 0.0f)) {
+        set_error("mlp_loss_grad: invalid arguments (batch %lld)", (long long)batch);
+        return HAWKES_EINVAL;
+    }
+    const TrainLayout T = train_layout(batch);
+    if (!ws || !aligned256(ws) || ws_bytes < T.total) {
+        set_error("mlp_loss_grad: workspace of %zu bytes, need %zu (256-byte aligned)", ws_bytes, T.total);
+        return HAWKES_EWORKSPACE;
+    }
+    char *w = static_cast<char *>(ws);
+    TrainWs t{reinterpret_cast<float *>(w + T.vec), reinterpret_cast<float *>(w + T.zr),
+              reinterpret_cast<float *>(w + T.cf), reinterpret_cast<float *>(w + T.loss)};
+    float *grad = d_grad ? d_grad : reinterpret_cast<float *>(w + T.grad);
+    hipStream_t st = as_stream(stream);
+    hipLaunchKernelGGL(k_mlp_train_sample, dim3(unsigned(batch)), dim3(H), 0, st, net_of(d_state), d_z, d_y, d_g,
+                       batch, lambda_g, t);
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3(unsigned((P + 255) / 256)), dim3(256), 0, st, t, batch,
+                       2.0f * lambda_g / float(batch), grad);
+    hipLaunchKernelGGL(k_mlp_loss_reduce, dim3(1), dim3(256), 0, st, t.loss, batch, d_loss);
+    return check_launch("mlp_loss_grad");
+}
+
+extern "C" int hawkes_mlp_adam_step(void *d_state, const float *d_grad, int64_t step, float lr, float beta1,
+                                    float beta2, float eps, void *stream)
+{
+    if (!d_state || !d_grad || !aligned256(d_state) || step < 1 || !(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) ||
+        !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f)) {
+        set_error("mlp_adam_step: invalid arguments");
+        return HAWKES_EINVAL;
+    }
+    const StateLayout L = state_layout();
+    char *s = static_cast<char *>(d_state);
+    const float c1 = float(1.0 - std::pow(double(beta1), double(step)));
+    const float c2 = float(1.0 - std::pow(double(beta2), double(step)));
+    const unsigned blocks = unsigned((P + 255) / 256);
+    hipStream_t st = as_stream(stream);
+    hipLaunchKernelGGL(k_mlp_adam, dim3(blocks), dim3(256), 0, st, reinterpret_cast<float *>(s + L.master),
+                       reinterpret_cast<float *>(s + L.m), reinterpret_cast<float *>(s + L.v), d_grad, lr, beta1, beta2,
+                       eps, c1, c2);
+    hipLaunchKernelGGL(k_mlp_refresh, dim3(blocks), dim3(256), 0, st, reinterpret_cast<const float *>(s + L.master),
+                       reinterpret_cast<uint16_t *>(s + L.wb), reinterpret_cast<uint16_t *>(s + L.wt2),
+                       reinterpret_cast<uint16_t *>(s + L.wt3));
+    return check_launch("mlp_adam_step");
+}

@@ -1,0 +1,129 @@
+"""CPU tests of the sampler layer on analytic targets (no GPU)."""
+
+import numpy as np
+import pytest
+
+from paper_2407_11349_amd.mcmc import DelayedAcceptanceHMC, HMC, bulk_ess, ess, mcse_mean, split_rhat
+
+
+def _ar1(rho, n, chains, seed):
+    rng = np.random.default_rng(seed)
+    x = np.zeros((chains, n))
+    e = rng.normal(size=(chains, n)) * np.sqrt(1 - rho**2)
+    x[:, 0] = rng.normal(size=chains)
+    for t in range(1, n):
+        x[:, t] = rho * x[:, t - 1] + e[:, t]
+    return x
+
+
+@pytest.mark.parametrize("rho", [0.0, 0.5, 0.9])
+def test_ess_matches_ar1_closed_form(rho):
+    """ESS of an AR(1) series is n (1 - rho) / (1 + rho)."""
+    x = _ar1(rho, 20000, 4, seed=int(rho * 10))
+    expect = x.size * (1 - rho) / (1 + rho)
+    assert ess(x) == pytest.approx(expect, rel=0.1)
+    assert bulk_ess(x) == pytest.approx(expect, rel=0.1)
+    assert split_rhat(x) < 1.01
+
+
+def test_rhat_flags_chains_that_disagree():
+    x = _ar1(0.5, 2000, 4, seed=3)
+    x[0] += 1.0
+    assert split_rhat(x) > 1.1
+
+
+class Gauss:
+    def __init__(self, mu, Q):
+        self.mu, self.Q = np.asarray(mu), np.asarray(Q)
+        self.calls = 0
+
+    def logp(self, z):
+        d = z - self.mu
+        self.calls += 1
+        return -0.5 * d @ self.Q @ d
+
+    def logp_and_grad(self, z):
+        d = z - self.mu
+        self.calls += 1
+        return -0.5 * d @ self.Q @ d, -(self.Q @ d)
+
+
+def _target(seed=0):
+    rng = np.random.default_rng(seed)
+    A = rng.normal(size=(6, 6))
+    C = A @ A.T / 6 + 0.2 * np.eye(6)
+    mu = rng.normal(size=6)
+    return Gauss(mu, np.linalg.inv(C)), mu, C
+
+
+def _check_moments(draws, mu, C, k=4.5):
+    for i in range(6):
+        se = mcse_mean(draws[:, i][None, :])
+        assert abs(draws[:, i].mean() - mu[i]) < k * se + 1e-3, (i, draws[:, i].mean(), mu[i], se)
+    np.testing.assert_allclose(np.cov(draws.T).diagonal(), C.diagonal(), rtol=0.25)
+
+
+def test_hmc_recovers_gaussian_moments():
+    tgt, mu, C = _target(0)
+    hmc = HMC(tgt, n_leapfrog=20, step_size=0.1, rng=np.random.default_rng(1))
+    s = hmc.init_state(np.zeros(6))
+    s = hmc.warmup(s, 400)
+    draws, acc = [], 0
+    for _ in range(3000):
+        s, a, _ = hmc.step(s)
+        acc += a
+        draws.append(s.z)
+    draws = np.array(draws)
+    assert 0.5 < acc / 3000 <= 1.0
+    _check_moments(draws, mu, C)
+
+
+def test_delayed_acceptance_is_exact_with_a_wrong_surrogate():
+    """The surrogate is a Gaussian with a shifted mean and inflated covariance; the DA kernel
+    must still sample the exact target."""
+    tgt, mu, C = _target(1)
+    bad = Gauss(mu + 0.3 * np.sqrt(C.diagonal()), np.linalg.inv(1.5 * C))
+    hmc = HMC(tgt, n_leapfrog=20, step_size=0.1, rng=np.random.default_rng(2))
+    s = hmc.warmup(hmc.init_state(np.zeros(6)), 400)
+    da = DelayedAcceptanceHMC(tgt, bad.logp_and_grad, n_leapfrog=20, step_size=hmc.eps, inv_mass=hmc.inv_mass,
+                              rng=np.random.default_rng(3), fallback_below=0.0)
+    st = da.init_state(s.z)
+    draws = []
+    for _ in range(6000):
+        st, _, _ = da.step(st)
+        draws.append(st.z)
+    draws = np.array(draws)
+    assert da.stats["stage1_accept"] > da.stats["stage2_accept"] > 0
+    _check_moments(draws, mu, C)
+
+
+def test_fallback_to_exact_hmc_when_acceptance_collapses():
+    """A surrogate pointing far away makes stage 2 reject; the windowed acceptance drops below
+    0.5 and exact HMC steps take over, still sampling the target."""
+    tgt, mu, C = _target(2)
+    awful = Gauss(mu + 8.0, np.linalg.inv(0.05 * C))
+    hmc = HMC(tgt, n_leapfrog=20, step_size=0.1, rng=np.random.default_rng(4))
+    s = hmc.warmup(hmc.init_state(np.zeros(6)), 400)
+    da = DelayedAcceptanceHMC(tgt, awful.logp_and_grad, n_leapfrog=20, step_size=hmc.eps, inv_mass=hmc.inv_mass,
+                              rng=np.random.default_rng(5), window=20, fallback_below=0.5)
+    st = da.init_state(s.z)
+    draws = []
+    for _ in range(3000):
+        st, _, _ = da.step(st)
+        draws.append(st.z)
+    assert da.stats["fallback"] > 1000
+    _check_moments(np.array(draws), mu, C)
+
+
+def test_good_surrogate_needs_few_exact_evaluations():
+    """With the exact density as its own surrogate, stage 2 always accepts and each iteration costs
+    one exact log-density evaluation instead of n_leapfrog gradients."""
+    tgt, mu, C = _target(3)
+    sur = Gauss(mu, tgt.Q)
+    da = DelayedAcceptanceHMC(tgt, sur.logp_and_grad, n_leapfrog=20, step_size=0.1, rng=np.random.default_rng(6))
+    st = da.init_state(np.zeros(6))
+    tgt.calls = 0
+    for _ in range(500):
+        st, _, _ = da.step(st)
+    assert da.stats["stage2_accept"] == da.stats["stage1_accept"]
+    assert tgt.calls == da.stats["stage1_accept"] <= 500
