@@ -37,6 +37,34 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash() -> str:
+    """Hash of the pair-sweep source: traffic counters are valid only for the kernel they measured."""
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_2407_11349_amd", "csrc", "hawkes_loglik.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic() -> float | None:
+    """HBM bytes per pair-sweep launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "pair_f32_n1m_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if line.startswith("|") and line.count("|") >= 3:
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) >= 2:
+                fields[cells[0]] = cells[1]
+    if fields.get("kernel source hash") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def pair_counts(t: np.ndarray) -> tuple[int, int]:
     """(background pairs, causal pairs) with ties excluded, from sorted times."""
     lo = np.searchsorted(t, t, side="left")
@@ -67,6 +95,24 @@ def cpu_baseline(ev, th, budget_s: float = 15.0) -> dict:
                       f"{dt:.1f} s"}
 
 
+def run_ess(args, hk, synth, torch):
+    """ESS/s of delayed-acceptance HMC with the BF16 surrogate against plain exact-gradient HMC, both on the
+    cut posterior (X redrawn every iteration) with the FP32 GPU likelihood, 20 leapfrog steps."""
+    from paper_2407_11349_amd.mcmc.experiment import compare
+
+    cfg = synth.CONFIGS[1] if args.ess_n <= synth.CONFIGS[1].n else synth.CONFIGS[2]
+    ev = synth.generate(cfg, n=args.ess_n)
+    dev = hk.DeviceEvents.from_arrays(ev.t, ev.x, ev.y, ev.s, device="cuda")
+    county = torch.from_numpy(ev.county).cuda()
+    rect = torch.from_numpy(ev.rect).cuda()
+    out = compare(dev, county, rect, n_burn=args.ess_burn, n_iter=args.ess_iter, log=log)
+    res = {"metric": "ESS/s surrogate-HMC vs plain HMC", "value": out["ess_per_s_ratio"], "unit": "ratio",
+           "higher_is_better": True, "data": "synthetic",
+           "config": {"workload": cfg.name, "n_events": ev.n, "burn_in": args.ess_burn, "iterations": args.ess_iter,
+                      "leapfrog": 20, "step": "resample X + sampler iteration"}, "detail": out}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +121,13 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the event count (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--ess", action="store_true",
+                    help="run the surrogate-HMC vs plain-HMC ESS/s comparison instead (minutes of GPU time)")
+    ap.add_argument("--ess-n", type=int, default=100_000, help="events of the ESS comparison workload")
+    ap.add_argument("--ess-burn", type=int, default=1000)
+    ap.add_argument("--ess-iter", type=int, default=2000)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES device-to-device (scales the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the pair sweep of one GPU is the measured unit; "
@@ -83,8 +136,21 @@ def main():
 
     import torch
 
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": src.numel() * 4}))
+        return
+
     import synth
     import paper_2407_11349_amd as hk
+
+    if args.ess:
+        run_ess(args, hk, synth, torch)
+        return
 
     cfg = synth.CONFIGS[2]
     ev = synth.generate(cfg, n=args.n)
@@ -141,7 +207,7 @@ def main():
         "loglik_grad_evals_per_s": 1e3 / ms_step,
         "roofline": {"bound": "alu", "kernel": "k_pair_f32<grad>", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": None, "kernel_ms": kms, "flop_per_launch": flop_per_launch,
+                     "traffic": measured_traffic(), "kernel_ms": kms, "kernel_source_hash": kernel_source_hash(), "flop_per_launch": flop_per_launch,
                      "exp_per_launch": exp_per_launch, "exp_per_s": exp_per_launch / (kms / 1e3)},
     }
 

@@ -1,0 +1,192 @@
+"""Surrogate training from HMC burn-in and the ESS/s comparison of plain HMC
+with surrogate delayed-acceptance HMC, on the cut posterior with the GPU
+likelihood (latent locations redrawn every iteration).
+
+Pipeline:
+  1. exact-HMC burn-in (step size and diagonal mass adapted); every leapfrog
+     point's (log theta, l, d l / d log theta) tuple is recorded;
+  2. the surrogate is trained on the tuples (90/10 split) with the Sobolev
+     loss, by the HIP train kernels; held-out errors are reported;
+  3. from the burn-in end state, plain HMC and DA-HMC run the same number of
+     iterations; ESS/s = min over the six parameters of bulk-ESS / wall
+     seconds, reported with and without the surrogate's training cost.
+"""
+
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from .cut import HawkesCutTarget
+from .da_hmc import DelayedAcceptanceHMC
+from .ess import bulk_ess, mcse_mean, split_rhat
+from .hmc import HMC, DualAveraging
+from ..surrogate import Standardiser, Surrogate, SurrogateNet, train
+
+
+def _sync():
+    """Waits for queued GPU work, so wall-clock intervals cover it (no-op before any GPU use)."""
+    if torch.cuda.is_initialized():
+        torch.cuda.synchronize()
+
+
+class RecordingTarget:
+    """Wraps a target and records (z, loglik, grad loglik wrt z) at every gradient evaluation."""
+
+    def __init__(self, target: HawkesCutTarget):
+        self.t = target
+        self.z, self.ll, self.g = [], [], []
+
+    def logp(self, z):
+        return self.t.logp(z)
+
+    def logp_and_grad(self, z):
+        lp, g = self.t.logp_and_grad(z)
+        if np.isfinite(lp):
+            z = np.asarray(z, dtype=np.float64)
+            prior_lp, prior_g = self.t._prior(z)
+            self.z.append(z.copy())
+            self.ll.append(lp - prior_lp)
+            self.g.append(g - prior_g)
+        return lp, g
+
+
+@dataclass
+class ChainResult:
+    draws: np.ndarray
+    seconds: float
+    n_loglik: int
+    n_grad: int
+    stats: dict
+
+
+def _summary(draws: np.ndarray) -> dict:
+    return {
+        "mean": draws.mean(axis=0).tolist(),
+        "mcse": [mcse_mean(draws[:, i][None, :]) for i in range(draws.shape[1])],
+        "bulk_ess": [bulk_ess(draws[:, i][None, :]) for i in range(draws.shape[1])],
+        "rhat": [split_rhat(draws[:, i][None, :]) for i in range(draws.shape[1])],
+    }
+
+
+def burn_in(target: HawkesCutTarget, z0, n_iter: int, n_leapfrog=20, seed=0, log=None):
+    """Exact HMC from z0 with step-size and mass adaptation; records every gradient evaluation."""
+    rec = RecordingTarget(target)
+    hmc = HMC(rec, n_leapfrog=n_leapfrog, step_size=0.01, rng=np.random.default_rng(seed))
+    t0 = time.time()
+    target.resample(0)
+    s = hmc.init_state(z0)
+    da = DualAveraging(np.log(hmc.eps), target=0.8)
+    draws = []
+    half = n_iter // 2
+    for it in range(n_iter):
+        s, _, a = hmc.step(s)
+        hmc.eps = da.update(a)
+        draws.append(s.z.copy())
+        if it + 1 == half and half >= 20:
+            var = np.array(draws[half // 2:]).var(axis=0)
+            if np.all(var > 0):
+                hmc.inv_mass = var
+            da = DualAveraging(np.log(hmc.eps), target=0.8)
+        # cut posterior: a new X draw, then the exact density and gradient under it
+        target.resample(it + 1)
+        s = hmc.init_state(s.z)
+        if log and (it + 1) % 100 == 0:
+            log(f"burn-in {it + 1}/{n_iter}: eps {hmc.eps:.3g} z {np.round(s.z, 4)}")
+    hmc.eps = da.final()
+    hmc.target = target
+    return hmc, s, rec, time.time() - t0
+
+
+def run_plain_hmc(target: HawkesCutTarget, hmc: HMC, z0, n_iter: int, it0: int, log=None) -> ChainResult:
+    n0, g0 = target.n_loglik, target.n_grad
+    _sync()
+    t0 = time.time()
+    target.resample(it0)
+    s = hmc.init_state(z0)
+    draws = []
+    acc = 0
+    for it in range(n_iter):
+        s, a, _ = hmc.step(s)
+        acc += a
+        draws.append(s.z.copy())
+        target.resample(it0 + it + 1)
+        s = hmc.init_state(s.z)
+        if log and (it + 1) % 200 == 0:
+            log(f"hmc {it + 1}/{n_iter}: accept {acc / (it + 1):.2f}")
+    _sync()
+    return ChainResult(np.array(draws), time.time() - t0, target.n_loglik - n0, target.n_grad - g0,
+                       {"accept": acc / n_iter})
+
+
+def run_da_hmc(target: HawkesCutTarget, sur: Surrogate, hmc: HMC, z0, n_iter: int, it0: int, prior_var: float,
+               log=None) -> ChainResult:
+    def sur_post(z):
+        ll, g = sur.value_and_grad(z)
+        return float(ll[0]) - 0.5 * float(np.dot(z, z)) / prior_var, g[0] - np.asarray(z) / prior_var
+
+    da = DelayedAcceptanceHMC(target, sur_post, n_leapfrog=hmc.n_leapfrog, step_size=hmc.eps,
+                              inv_mass=hmc.inv_mass, rng=np.random.default_rng(11))
+    n0, g0 = target.n_loglik, target.n_grad
+    _sync()
+    t0 = time.time()
+    target.resample(it0)
+    st = da.init_state(z0)
+    draws = []
+    for it in range(n_iter):
+        st, _, _ = da.step(st)
+        draws.append(st.z.copy())
+        target.resample(it0 + it + 1)
+        st = da.refresh_exact(st)
+        if log and (it + 1) % 200 == 0:
+            log(f"da-hmc {it + 1}/{n_iter}: {da.stats}")
+    _sync()
+    return ChainResult(np.array(draws), time.time() - t0, target.n_loglik - n0, target.n_grad - g0, dict(da.stats))
+
+
+def compare(events, county, rect, *, n_burn=1000, n_iter=2000, n_leapfrog=20, seed=2002, lam=1.0, epochs=60,
+            log=None) -> dict:
+    from synth.mlp_init import init_params
+
+    target = HawkesCutTarget(events, county, rect, seed=seed, precision="fp32")
+    z0 = np.log(np.array([0.5, 10.0, 7.0, 0.3, 2.0, 0.2]))
+    hmc, st, rec, t_burn = burn_in(target, z0, n_burn, n_leapfrog, seed=1, log=log)
+    Zt, Lt, Gt = np.array(rec.z), np.array(rec.ll), np.array(rec.g)
+    n = Zt.shape[0]
+    rng = np.random.default_rng(7)
+    perm = rng.permutation(n)
+    tr, te = perm[: int(0.9 * n)], perm[int(0.9 * n):]
+    std = Standardiser.fit(Zt[tr], Lt[tr])
+    t0 = time.time()
+    net = SurrogateNet(init_params(3))
+    hist = train(net, std, Zt[tr], Lt[tr], Gt[tr], lam=lam, epochs=epochs, batch=256, lr=1e-3, seed=5)
+    _sync()
+    t_train = time.time() - t0
+    sur = Surrogate(net, std)
+    yh, gh = sur.value_and_grad(Zt[te])
+    # the X draw shifts l by a near-constant; errors are reported after removing the mean offset
+    err = yh - Lt[te]
+    held = {"tuples": int(n), "train_seconds": t_train, "final_loss": hist[-1],
+            "loglik_rmse": float(np.sqrt(np.mean((err - err.mean()) ** 2))),
+            "loglik_offset": float(err.mean()), "loglik_spread": float(Lt[te].std()),
+            "grad_rel_rmse": float(np.sqrt(np.mean((gh - Gt[te]) ** 2)) / np.sqrt(np.mean(Gt[te] ** 2)))}
+    if log:
+        log(f"surrogate: {held}")
+    it0 = n_burn + 1
+    plain = run_plain_hmc(target, hmc, st.z, n_iter, it0, log=log)
+    dah = run_da_hmc(target, sur, hmc, st.z, n_iter, it0 + n_iter + 1, target.prior_var, log=log)
+    out = {"burn_in_seconds": t_burn, "surrogate": held, "step_size": hmc.eps, "n_iter": n_iter}
+    for name, r in (("plain_hmc", plain), ("da_hmc", dah)):
+        s = _summary(r.draws)
+        ess_min = float(np.min(s["bulk_ess"]))
+        out[name] = {"seconds": r.seconds, "n_loglik": r.n_loglik, "n_grad": r.n_grad, "stats": r.stats,
+                     "min_bulk_ess": ess_min, "ess_per_s": ess_min / r.seconds, **s}
+    out["da_hmc"]["ess_per_s_incl_training"] = out["da_hmc"]["min_bulk_ess"] / (dah.seconds + t_train)
+    mp, md = np.array(out["plain_hmc"]["mean"]), np.array(out["da_hmc"]["mean"])
+    se = np.sqrt(np.array(out["plain_hmc"]["mcse"]) ** 2 + np.array(out["da_hmc"]["mcse"]) ** 2)
+    out["means_agree_within_3_mcse"] = bool(np.all(np.abs(mp - md) <= 3 * se))
+    out["ess_per_s_ratio"] = out["da_hmc"]["ess_per_s"] / out["plain_hmc"]["ess_per_s"]
+    return out
