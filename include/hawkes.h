@@ -67,8 +67,15 @@ typedef struct hawkes_events {
 /* Arithmetic of the O(N^2) pair sweep.  FP64: every pair term in FP64.
  * FP32: pair terms in FP32 (pair differences formed in FP64 and rounded once,
  * per-tile FP32 partial sums folded into FP64 accumulators); the per-event
- * log, the compensator and all reductions stay in FP64. */
-enum hawkes_precision { HAWKES_FP64 = 0, HAWKES_FP32 = 1 };
+ * log, the compensator and all reductions stay in FP64.
+ * FP32_SKIP: the FP32 sweep, leaving out every background term that is
+ * exactly zero in FP32 because the scaled time gap alone makes its exponent
+ * exceed 160 (|t_n - t_m| > sqrt(2 * 160 / log2(e)) tau_t, about 14.9 tau_t):
+ * whole source tiles that late are not visited and tiles that early sweep the
+ * triggering terms only.  The result equals FP32 up to the FP64 summation
+ * order of the chunk partials (identical when each chunk is one tile); the
+ * work falls when the time span is long against tau_t. */
+enum hawkes_precision { HAWKES_FP64 = 0, HAWKES_FP32 = 1, HAWKES_FP32_SKIP = 2 };
 
 enum hawkes_status {
     HAWKES_OK = 0,
@@ -135,7 +142,7 @@ int hawkes_last_pair_kernel_ms(float *ms);
 
 /* Tuning: the number of workgroups the pair sweep aims for per call (the
  * source range is split into chunks so that target blocks x chunks is about
- * this many; 1 <= wgs <= 16384; default 4096).  Results do not depend on it
+ * this many; 1 <= wgs <= 65536; default 32768).  Results do not depend on it
  * beyond FP rounding of the chunk partial sums.  Process-wide setting. */
 int hawkes_tune_target_workgroups(int64_t wgs);
 

@@ -17,7 +17,9 @@ LIB_PATH = Path(__file__).resolve().parent / "libhawkes.so"
 
 HAWKES_FP64 = 0
 HAWKES_FP32 = 1
-PRECISIONS = {"fp64": HAWKES_FP64, "fp32": HAWKES_FP32, HAWKES_FP64: HAWKES_FP64, HAWKES_FP32: HAWKES_FP32}
+HAWKES_FP32_SKIP = 2
+PRECISIONS = {"fp64": HAWKES_FP64, "fp32": HAWKES_FP32, "fp32_skip": HAWKES_FP32_SKIP,
+              HAWKES_FP64: HAWKES_FP64, HAWKES_FP32: HAWKES_FP32, HAWKES_FP32_SKIP: HAWKES_FP32_SKIP}
 
 HAWKES_OK = 0
 HAWKES_EORDER = -5

@@ -24,7 +24,7 @@
 //   lambda_n = mu c_b S0 + xi c_g G0, and every d lambda_n / d theta is a
 //   linear combination of the six sums.
 //
-// Work decomposition: a workgroup owns TB = 1024 target rows (4 per lane) and
+// Work decomposition: a workgroup owns TB = 512 target rows (2 per lane) and
 // one chunk of source tiles; TS = 256 sources per tile are staged through LDS
 // (double buffered) and read by all lanes as broadcasts.  Each
 // (target block, tile) pair is classified from the tile's and the block's
@@ -32,6 +32,10 @@
 // background + triggering, no masks), ANTI (every source strictly later:
 // background only) or MIXED (per-pair masks from tie-group ids).  Causality
 // is never decided from rounded times.
+//
+// Skip mode (HAWKES_FP32_SKIP): the same FP32 sweep without the pairs whose
+// background term is exactly zero in FP32 because the time gap alone puts its
+// exponent past the subnormal range; same results, less work on long spans.
 //
 // FP32 arithmetic (precision HAWKES_FP32):
 //  * positions are pre-scaled in FP64 by sqrt(log2(e)/(2 tau_x^2)) and times
@@ -60,12 +64,26 @@ namespace hawkes {
 
 namespace {
 
+// Compile-time shape of the FP32 sweep (defaults measured fastest on gfx950;
+// the macros exist so that other shapes can be built and timed).
+#ifndef HAWKES_KT
+#define HAWKES_KT 2
+#endif
+#ifndef HAWKES_GS
+#define HAWKES_GS 8
+#endif
+#ifndef HAWKES_UJ
+#define HAWKES_UJ HAWKES_GS
+#endif
+#define HK_STR(x) #x
+#define HK_UNROLL(n) _Pragma(HK_STR(unroll n))
+
 constexpr int TS = 256;                   // sources per LDS tile
 constexpr int WG = 256;                   // threads per workgroup (4 wave64)
-constexpr int KT = 4;                     // target rows per lane
+constexpr int KT = HAWKES_KT;             // target rows per lane
 constexpr int TB = WG * KT;               // target rows per workgroup
-constexpr int GS = 8;                     // FP32 terms summed before folding into FP64
-constexpr int64_t MAX_TARGET_WGS = 16384; // upper bound used for workspace sizing
+constexpr int GS = HAWKES_GS;             // FP32 terms summed before folding into FP64
+constexpr int64_t MAX_TARGET_WGS = 65536; // upper bound used for workspace sizing
 constexpr int64_t MAX_N = int64_t(1) << 30;
 constexpr double LOG2E = 1.4426950408889634074;
 constexpr double LAMBDA_FLOOR = 1e-40;
@@ -79,6 +97,10 @@ constexpr double EXP2_MEAN_REL_ERR = -3.41e-9;
 // Rows whose FP32 rate may have lost more than this fraction of its value to
 // FP32 underflow (terms below 2^-126) are recomputed in FP64.
 constexpr double RESCUE_REL = 1e-12;
+// Background exponents (in units of log2) at or above this give exp2 = 0 in
+// FP32 (the smallest subnormal is 2^-149); the skip mode leaves out pairs
+// whose scaled time gap alone reaches it.
+constexpr double SKIP_EXPONENT = 160.0;
 
 constexpr int STATUS_ORDER = 1;
 constexpr int STATUS_DATA = 2;
@@ -86,6 +108,8 @@ constexpr int STATUS_DATA = 2;
 enum TileClass { CAUSAL = 0, ANTI = 1, MIXED = 2 };
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+inline bool is_fp32(int precision) { return precision == HAWKES_FP32 || precision == HAWKES_FP32_SKIP; }
+inline bool valid_precision(int precision) { return precision == HAWKES_FP64 || is_fp32(precision); }
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ------------------------------------------------------------------ layout
@@ -120,7 +144,7 @@ Layout make_layout(int64_t n, int precision)
     L.status = take(256);
     L.g = take(sizeof(int) * L.n_pad);
     L.tile = take(sizeof(double) * 3 * L.num_tiles);
-    if (precision == HAWKES_FP32) {
+    if (is_fp32(precision)) {
         L.xs = take(sizeof(double) * L.n_pad);
         L.ys = take(sizeof(double) * L.n_pad);
         L.tsd = take(sizeof(double) * L.n_pad);
@@ -145,7 +169,7 @@ struct Plan {
     int64_t rows = 0, num_tb = 0, rows_pad = 0, chunk_tiles = 0, num_chunks = 0;
 };
 
-int64_t g_target_wgs = 4096;
+int64_t g_target_wgs = 32768;
 
 Plan make_plan(int64_t rows, int64_t num_tiles)
 {
@@ -287,6 +311,13 @@ struct PairF32 {
     int64_t row_begin, row_end, rows_pad, num_tiles, chunk_tiles, num_chunks, num_tb;
     double omega, inv_st, out_s1, out_s2, out_g1, out_exp;
     double w2;  // omega * log2(e) / time scale: the triggering exponent per scaled day
+    // Skip mode: every background term of a pair further apart in time than
+    // skip_gap days is exactly zero in FP32.  Tiles that far after the block
+    // are not visited (window = 1: each block splits only the tiles it visits
+    // into chunks) and tiles that far before it sweep the triggering terms
+    // only.  Without skipping, skip_gap is infinite and window = 0.
+    double skip_gap;
+    int window;
 };
 
 // The FP32 fused sweep.  GRAD = false keeps only S0 and G0 (log-likelihood).
@@ -298,8 +329,18 @@ struct PairF32 {
 //   with t1 = r_m D.  Every FP32 value that many pairs would share is split
 //   hi + lo, and every rounding left is of a value that varies from pair to
 //   pair, so rounding errors average out instead of adding up.
+// At least this many waves per SIMD: the register budget the compiler must
+// fit (2 waves = 256 registers per lane).  KT = 2 needs ~166 and runs at 3.
+#ifndef HAWKES_WAVES_PER_EU
+#define HAWKES_WAVES_PER_EU 2
+#endif
+#if HAWKES_WAVES_PER_EU > 0
+#define HK_PAIR_ATTR __attribute__((amdgpu_waves_per_eu(HAWKES_WAVES_PER_EU)))
+#else
+#define HK_PAIR_ATTR
+#endif
 template <bool GRAD>
-__global__ __launch_bounds__(WG) void k_pair_f32(PairF32 a)
+__global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
 {
     __shared__ double lx[2][TS], ly[2][TS], lt[2][TS];
     __shared__ float lrh[2][TS], lrl[2][TS], lvh[2][TS], lvl[2][TS], ld[2][TS], luh[2][TS], lul[2][TS];
@@ -333,8 +374,23 @@ __global__ __launch_bounds__(WG) void k_pair_f32(PairF32 a)
         for (int z = 0; z < 6; ++z)
             acc[q][z] = 0.0;
 
-    const int64_t k0 = chunk * a.chunk_tiles;
-    const int64_t k1 = (k0 + a.chunk_tiles < a.num_tiles) ? k0 + a.chunk_tiles : a.num_tiles;
+    int64_t k_end = a.num_tiles, chunk_tiles = a.chunk_tiles;
+    if (a.window) {
+        // first tile that starts more than skip_gap days after the block ends
+        const double limit = t_hi + a.skip_gap;
+        int64_t lo = 0, hi = a.num_tiles;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (a.tile[3 * mid + 0] > limit)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        k_end = lo;
+        chunk_tiles = (k_end + a.num_chunks - 1) / a.num_chunks;
+    }
+    const int64_t k0 = chunk * chunk_tiles;
+    const int64_t k1 = (k0 + chunk_tiles < k_end) ? k0 + chunk_tiles : k_end;
 
     struct Rec {
         double x, y, t;
@@ -359,7 +415,8 @@ __global__ __launch_bounds__(WG) void k_pair_f32(PairF32 a)
         lg[buf][tid] = r.g;
     };
 
-    store(fetch(k0), 0);
+    if (k0 < k1)
+        store(fetch(k0), 0);
     __syncthreads();
 
     for (int64_t k = k0; k < k1; ++k) {
@@ -371,6 +428,7 @@ __global__ __launch_bounds__(WG) void k_pair_f32(PairF32 a)
 
         const double first = a.tile[3 * k + 0], last = a.tile[3 * k + 1];
         const int cls = (last < t_lo) ? CAUSAL : ((first > t_hi) ? ANTI : MIXED);
+        const bool trig_only = (cls == CAUSAL) && (t_lo - last > a.skip_gap);
 
         // Terms are summed in FP32 over groups of GS = 8 sources and each
         // group sum is folded into FP64.  Long FP32 running sums would round
@@ -399,8 +457,28 @@ __global__ __launch_bounds__(WG) void k_pair_f32(PairF32 a)
 #pragma unroll
                     for (int z = 0; z < 6; ++z)
                         f[q][z] = 0.0f;
-                if (causal) {
+                if (trig_only) {
+                    HK_UNROLL(HAWKES_UJ)
+                    for (int j = 0; j < GS; ++j) {
+                        const int m = m0 + j;
+                        const double xm = sx[m], ym = sy[m];
+                        const float rhm = srh[m], rlm = srl[m], vhm = svh[m], vlm = svl[m], dm = sd[m];
 #pragma unroll
+                        for (int q = 0; q < KT; ++q) {
+                            const double dx = xn[q] - xm, dy = yn[q] - ym;
+                            const float D = float(fma(dy, dy, dx * dx));
+                            const float t1 = fmaf(rlm, D, rhm * D);
+                            const float E = __builtin_amdgcn_exp2f(-t1);
+                            const float p = fmaf(vlm, E, vhm * E);
+                            f[q][3] += p;
+                            if (GRAD) {
+                                f[q][4] = fmaf(p, t1, f[q][4]);
+                                f[q][5] = fmaf(p, dm, f[q][5]);
+                            }
+                        }
+                    }
+                } else if (causal) {
+                    HK_UNROLL(HAWKES_UJ)
                     for (int j = 0; j < GS; ++j) {
                         const int m = m0 + j;
                         const double xm = sx[m], ym = sy[m], tm = st[m];
@@ -426,7 +504,7 @@ __global__ __launch_bounds__(WG) void k_pair_f32(PairF32 a)
                         }
                     }
                 } else {
-#pragma unroll
+                    HK_UNROLL(HAWKES_UJ)
                     for (int j = 0; j < GS; ++j) {
                         const int m = m0 + j;
                         const double xm = sx[m], ym = sy[m], tm = st[m];
@@ -447,10 +525,12 @@ __global__ __launch_bounds__(WG) void k_pair_f32(PairF32 a)
                 }
 #pragma unroll
                 for (int q = 0; q < KT; ++q) {
-                    acc[q][0] += double(f[q][0]);
-                    if (GRAD) {
-                        acc[q][1] += double(f[q][1]);
-                        acc[q][2] += double(f[q][2]);
+                    if (!trig_only) {
+                        acc[q][0] += double(f[q][0]);
+                        if (GRAD) {
+                            acc[q][1] += double(f[q][1]);
+                            acc[q][2] += double(f[q][2]);
+                        }
                     }
                     if (causal) {
                         gt[q][0] += double(f[q][3]);
@@ -937,8 +1017,8 @@ int validate(const hawkes_events *ev, const hawkes_theta *th, int precision, int
         set_error("null event array");
         return HAWKES_EINVAL;
     }
-    if (precision != HAWKES_FP64 && precision != HAWKES_FP32) {
-        set_error("precision %d is neither HAWKES_FP64 nor HAWKES_FP32", precision);
+    if (!valid_precision(precision)) {
+        set_error("precision %d is not HAWKES_FP64, HAWKES_FP32 or HAWKES_FP32_SKIP", precision);
         return HAWKES_EINVAL;
     }
     const double p[6] = {th->mu, th->tau_x, th->tau_t, th->xi, th->h0, th->omega};
@@ -1014,7 +1094,7 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
     double *partials = at<double>(ws, L.partials);
     const unsigned pair_blocks = unsigned(P.num_tb * P.num_chunks);
 
-    if (precision == HAWKES_FP32) {
+    if (is_fp32(precision)) {
         StageF32 sc;
         sc.sx = std::sqrt(LOG2E / (2.0 * tau_x * tau_x));
         sc.st = std::sqrt(LOG2E / (2.0 * tau_t * tau_t));
@@ -1057,6 +1137,14 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
         a.out_g1 = 2.0 * h0 * h0 / LOG2E;        // t1 = u d^2 log2(e) / (2 h0^2)
         a.w2 = omega * LOG2E / sc.st;
         a.out_exp = 1.0 / (1.0 + EXP2_MEAN_REL_ERR);
+        if (precision == HAWKES_FP32_SKIP) {
+            // scaled time gap whose square exceeds 160: exp2(-A) <= 2^-160 is 0 in FP32
+            a.skip_gap = std::sqrt(SKIP_EXPONENT) / sc.st;
+            a.window = 1;
+        } else {
+            a.skip_gap = HUGE_VAL;
+            a.window = 0;
+        }
         if (g_timing && (rc = record_event(g_ev_start, stream)) != HAWKES_OK)
             return rc;
         if (grad)
@@ -1138,7 +1226,7 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
     // Each FP32 pair term below 2^-126 may be lost to underflow; n of them
     // bound the loss by n 2^-126 (mu c_b + xi c_g).  Rows whose rate is not
     // 1/RESCUE_REL times larger than that are recomputed in FP64.
-    f.rescue_lambda = (precision == HAWKES_FP32)
+    f.rescue_lambda = is_fp32(precision)
                           ? double(n) * std::ldexp(1.0, -126) * (f.mu * f.c_b + f.xi * f.c_g) / RESCUE_REL
                           : 0.0;
     const int64_t nblk = ceil_div(rows, 256);
@@ -1148,7 +1236,7 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
         hipLaunchKernelGGL(k_finalize<false>, dim3(unsigned(nblk)), dim3(256), 0, stream, f);
     if ((rc = check_launch("finalize")) != HAWKES_OK)
         return rc;
-    if (precision == HAWKES_FP32) {
+    if (is_fp32(precision)) {
         const unsigned rescue_wgs = unsigned(nblk < 256 ? nblk : 256);
         if (grad)
             hipLaunchKernelGGL(k_rescue<true>, dim3(rescue_wgs), dim3(256), 0, stream, f);
@@ -1207,7 +1295,7 @@ using namespace hawkes;
 
 extern "C" size_t hawkes_workspace_bytes(int64_t n, int precision)
 {
-    if (n < 1 || n > MAX_N || (precision != HAWKES_FP64 && precision != HAWKES_FP32))
+    if (n < 1 || n > MAX_N || !valid_precision(precision))
         return 0;
     return make_layout(n, precision).total;
 }

@@ -2,7 +2,8 @@
 // exp2 (v_exp_f32, __builtin_amdgcn_exp2f) on gfx950 against FP64 exp2, over
 // FP32 arguments spread uniformly on several ranges.  The FP32 pair sweep
 // divides its sums by (1 + mean error) because every FP32 pair term carries
-// exactly one hardware exp2.
+// exactly one hardware exp2.  It also counts nonzero results of exp2 over
+// [-1000, -150]: a term whose exponent is below -150 is exactly zero.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -51,6 +52,17 @@ __global__ void bias_kernel(long long M, float lo, float hi, double *part)
     }
 }
 
+// number of x in [lo, hi) (M evenly spaced FP32 arguments) with exp2(x) != 0
+__global__ void nonzero_kernel(long long M, float lo, float hi, unsigned long long *count)
+{
+    unsigned long long c = 0;
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < M; i += (long long)gridDim.x * 256) {
+        const float x = lo + (hi - lo) * (float)((i + 0.5) / (double)M);
+        c += (__builtin_amdgcn_exp2f(x) != 0.0f) ? 1 : 0;
+    }
+    atomicAdd(count, c);
+}
+
 int main()
 {
     const long long M = 1LL << 30;
@@ -73,5 +85,15 @@ int main()
                M);
     }
     CHECK(hipFree(dpart));
+
+    unsigned long long *dcount, hcount = 0;
+    CHECK(hipMalloc(&dcount, sizeof(unsigned long long)));
+    CHECK(hipMemset(dcount, 0, sizeof(unsigned long long)));
+    const long long Mz = 1LL << 28;
+    hipLaunchKernelGGL(nonzero_kernel, dim3(blocks), dim3(256), 0, 0, Mz, -1000.f, -150.f, dcount);
+    CHECK(hipGetLastError());
+    CHECK(hipMemcpy(&hcount, dcount, sizeof(hcount), hipMemcpyDeviceToHost));
+    printf("exp2 on [-1000,-150]: %llu nonzero results of %lld\n", hcount, Mz);
+    CHECK(hipFree(dcount));
     return 0;
 }

@@ -57,9 +57,13 @@ def test_burn_in_records_tuples_and_chains_agree():
     mu = rng.normal(size=6) * 0.1
     Q = np.linalg.inv(C)
     tgt = FakeCutTarget(mu, Q)
-    hmc, st, rec, _ = ex.burn_in(tgt, mu + 0.05, 300, n_leapfrog=10, seed=1)
-    # every gradient evaluation is recorded with the prior removed
-    assert len(rec.z) == tgt.n_grad and len(rec.z) >= 300 * 10
+    n0 = tgt.n_grad
+    hmc, st, rec, _ = ex.burn_in(tgt, mu + 3.0, 300, n_leapfrog=10, seed=1, n_warmup=200)
+    # the mode search reaches the posterior from a distant start
+    assert np.all(np.abs(st.z - mu) < 1.0)
+    # after warm-up, every gradient evaluation is recorded with the prior removed:
+    # 10 leapfrog points and one start-of-iteration evaluation per iteration, plus the first
+    assert len(rec.z) == 300 * 11 + 1 and tgt.n_grad - n0 > len(rec.z)
     plain = ex.run_plain_hmc(tgt, hmc, st.z, 1500, it0=1000)
     da = ex.run_da_hmc(tgt, FakeSurrogate(mu, Q), hmc, st.z, 1500, it0=5000, prior_var=tgt.prior_var)
     # cost: plain HMC needs n_leapfrog + 1 gradients per iteration; DA one or two log-densities,

@@ -229,11 +229,11 @@ def test_chunking_does_not_change_results_beyond_rounding():
     lib = _lib.load()
     vals = []
     try:
-        for wgs in (1, 64, 4096, 16384):
+        for wgs in (1, 64, 4096, 65536):
             assert lib.hawkes_tune_target_workgroups(wgs) == 0
             vals.append(_gpu_ll_grad(dev, th, "fp32"))
     finally:
-        lib.hawkes_tune_target_workgroups(4096)
+        lib.hawkes_tune_target_workgroups(32768)
     for ll, g in vals[1:]:
         assert ll == pytest.approx(vals[0][0], rel=1e-11)
         np.testing.assert_allclose(g, vals[0][1], rtol=1e-8)

@@ -1,0 +1,115 @@
+"""GPU checks of the FP32 skip mode (HAWKES_FP32_SKIP): the FP32 sweep without the
+background terms that are exactly zero in FP32 because of the time gap alone.
+
+Its results equal those of the plain FP32 sweep (bitwise when every source chunk is one
+tile, else up to the FP64 summation order of the chunk partials) and so meet the same
+tolerances against the FP64 oracle."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+import paper_2407_11349_amd as hk
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_values.json")
+TOL_L, TOL_G, TOL_EV = 1e-9, 1e-6, 5e-6
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _run(dev, th, prec, rows=None):
+    ll, g = hk.loglik_grad(dev, th, precision=prec, rows=rows)
+    lam, comp = hk.event_terms(dev, th, precision=prec, rows=rows)
+    torch.cuda.synchronize()
+    return float(ll.item()), g.cpu().numpy(), lam.cpu().numpy(), comp.cpu().numpy()
+
+
+def _dev(ev, t=None):
+    return hk.DeviceEvents.from_arrays(ev.t if t is None else t, ev.x, ev.y, ev.s)
+
+
+def test_skip_is_bitwise_fp32_when_chunks_are_single_tiles():
+    # 2e4 events over 1000 days: 79 tiles, 20 target blocks, so every chunk is one tile
+    ev = synth.generate(1, n=20000, seed=31)
+    th = synth.theta_default()
+    dev = _dev(ev)
+    full = _run(dev, th, "fp32")
+    skip = _run(dev, th, "fp32_skip")
+    assert skip[0] == full[0]
+    for a, b in zip(skip[1:], full[1:]):
+        assert np.array_equal(a, b)
+    ll_ref, g_ref = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th)
+    _say(f"skip n20000: loglik rel err {abs(skip[0] - ll_ref) / abs(ll_ref):.2e}")
+    assert abs(skip[0] - ll_ref) <= TOL_L * abs(ll_ref)
+    np.testing.assert_allclose(skip[1], g_ref, rtol=TOL_G)
+
+
+def test_skip_config1_against_stored_oracle_and_fp32():
+    gold = json.load(open(GOLDEN))["n100k"]
+    ev = synth.generate(1)
+    th = np.array(gold["theta"])
+    dev = _dev(ev)
+    ll_s, g_s = hk.loglik_grad(dev, th, precision="fp32_skip")
+    ll_f, g_f = hk.loglik_grad(dev, th, precision="fp32")
+    ll_s, g_s, ll_f, g_f = float(ll_s.item()), g_s.cpu().numpy(), float(ll_f.item()), g_f.cpu().numpy()
+    rel_l = abs(ll_s - gold["loglik"]) / abs(gold["loglik"])
+    rel_g = np.max(np.abs(g_s - np.array(gold["grad"])) / np.abs(np.array(gold["grad"])))
+    _say(f"skip n100k: loglik rel err {rel_l:.2e}, grad rel err max {rel_g:.2e}")
+    assert rel_l <= TOL_L and rel_g <= TOL_G
+    # against the plain sweep: only the FP64 order of the chunk partials differs
+    assert abs(ll_s - ll_f) <= 1e-13 * abs(ll_f)
+    np.testing.assert_allclose(g_s, g_f, rtol=1e-11)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 257, 1025, 5003])
+def test_skip_ragged_sizes_per_event(n):
+    ev = synth.generate(0, n=n, seed=900 + n)
+    th = synth.theta_default()
+    th[2] = 0.5  # tau_t = 0.5 d over 100 days: most of the span is past the gap
+    _, _, lam_ref, comp_ref, _ = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th, per_row=True)
+    ll, g, lam, comp = _run(_dev(ev), th, "fp32_skip")
+    pos = lam_ref > 0
+    np.testing.assert_allclose(lam[pos], lam_ref[pos], rtol=TOL_EV)
+    np.testing.assert_allclose(comp, comp_ref, rtol=1e-13, atol=1e-13)
+    full = _run(_dev(ev), th, "fp32")
+    assert abs(ll - full[0]) <= 1e-13 * max(abs(full[0]), 1.0)
+    np.testing.assert_allclose(g, full[1], rtol=1e-11, atol=1e-300)
+
+
+def test_skip_short_tau_t_and_ties():
+    """Integer-day times (ties) and tau_t = 0.3 d: almost every earlier tile is swept for
+    the triggering terms only, almost every later one is not visited."""
+    ev = synth.generate(0, n=6000, seed=12)
+    t = np.floor(ev.t)
+    th = synth.theta_default()
+    th[2] = 0.3
+    ll_ref, g_ref, lam_ref, _, _ = oracle.loglik(t, ev.x, ev.y, ev.s, th, per_row=True)
+    ll, g, lam, _ = _run(_dev(ev, t), th, "fp32_skip")
+    np.testing.assert_allclose(lam, lam_ref, rtol=TOL_EV)
+    rel_l = abs(ll - ll_ref) / abs(ll_ref)
+    _say(f"skip ties tau_t=0.3: loglik rel err {rel_l:.2e}")
+    assert rel_l <= TOL_L
+    np.testing.assert_allclose(g, g_ref, rtol=TOL_G)
+
+
+def test_skip_row_ranges_add_up():
+    ev = synth.generate(1, n=30000, seed=5)
+    th = synth.theta_default()
+    dev = _dev(ev)
+    ll, g, _, _ = _run(dev, th, "fp32_skip")
+    cuts = [0, 1, 4096, 11111, 29999, 30000]
+    parts = [_run(dev, th, "fp32_skip", rows=(a, b)) for a, b in zip(cuts[:-1], cuts[1:])]
+    assert sum(p[0] for p in parts) == pytest.approx(ll, rel=TOL_L)
+    np.testing.assert_allclose(sum(p[1] for p in parts), g, rtol=TOL_G)
+    a, b = 11111, 29999
+    ref, _ = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th, rows=(a, b))
+    assert abs(parts[3][0] - ref) <= TOL_L * abs(ref) + 5e-7 * np.sqrt(b - a)
