@@ -40,7 +40,7 @@ def build_library(out: Path | None = None, verbose: bool = False) -> Path:
     return out
 
 
-PROBES = ["probe_exp2_bias", "probe_valu_rates"]
+PROBES = ["probe_exp2_bias", "probe_valu_rates", "probe_mfma_f64"]
 
 
 def build_probes() -> list[Path]:

@@ -75,6 +75,11 @@ namespace {
 #ifndef HAWKES_UJ
 #define HAWKES_UJ HAWKES_GS
 #endif
+// Pair geometry of the FP32 sweep: 0 = FP64 differences of pre-scaled
+// coordinates; 1 = exact int32 differences of fixed-point coordinates.
+#ifndef HAWKES_IGEOM
+#define HAWKES_IGEOM 0
+#endif
 #define HK_STR(x) #x
 #define HK_UNROLL(n) _Pragma(HK_STR(unroll n))
 
@@ -118,6 +123,7 @@ struct Layout {
     int64_t n = 0, n_pad = 0, num_tiles = 0, part_elems = 0, max_blocks = 0, rows_cap = 0;
     size_t status = 0, g = 0, tile = 0, rowvals = 0, rescue = 0;
     size_t xs = 0, ys = 0, tsd = 0, rh = 0, rl = 0, vh = 0, vl = 0, dl = 0, uh = 0, ul = 0;
+    size_t xi = 0, yi = 0, ti = 0;
     size_t partials = 0, blocks = 0, total = 0;
 };
 
@@ -155,6 +161,11 @@ Layout make_layout(int64_t n, int precision)
         L.dl = take(sizeof(float) * L.n_pad);
         L.uh = take(sizeof(float) * L.n_pad);
         L.ul = take(sizeof(float) * L.n_pad);
+        if (HAWKES_IGEOM) {
+            L.xi = take(sizeof(int) * L.n_pad);
+            L.yi = take(sizeof(int) * L.n_pad);
+            L.ti = take(sizeof(int) * L.n_pad);
+        }
     }
     L.partials = take(sizeof(double) * L.part_elems);
     L.blocks = take(sizeof(double) * 7 * L.max_blocks);
@@ -189,11 +200,49 @@ Plan make_plan(int64_t rows, int64_t num_tiles)
 
 // ------------------------------------------------------------- kernels
 
-// status[0]: data-check flags; status[1]: number of rows on the rescue list
+// status[0]: data-check flags; status[1]: number of rows on the rescue list.
+// Bytes 64..87 of the status block: maxima of |x|, |y|, |t| (FP64 bit
+// patterns, which order like the values for non-negative numbers); bytes
+// 128..143: the fixed-point quantum q and q^2 of the integer geometry.
+constexpr int STATUS_EXT = 8, STATUS_GEO = 16;  // offsets in 8-byte words
 __global__ void k_clear_status(int *status)
 {
     status[0] = 0;
     status[1] = 0;
+    unsigned long long *ext = reinterpret_cast<unsigned long long *>(status) + STATUS_EXT;
+    ext[0] = ext[1] = ext[2] = 0ull;
+}
+
+// Largest |x|, |y| and |t| of the events (one atomic per workgroup and value).
+__global__ __launch_bounds__(256) void k_extent(const double *__restrict__ t, const double *__restrict__ x,
+                                                const double *__restrict__ y, int64_t n, int *status)
+{
+    __shared__ double red[3][256];
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    double ax = 0.0, ay = 0.0, at = 0.0;
+    if (i < n) {
+        ax = fabs(x[i]);
+        ay = fabs(y[i]);
+        at = fabs(t[i]);
+        // non-finite values are flagged by the data checks; keep them out of the extents
+        ax = isfinite(ax) ? ax : 0.0;
+        ay = isfinite(ay) ? ay : 0.0;
+        at = isfinite(at) ? at : 0.0;
+    }
+    red[0][threadIdx.x] = ax;
+    red[1][threadIdx.x] = ay;
+    red[2][threadIdx.x] = at;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int z = 0; z < 3; ++z)
+                red[z][threadIdx.x] = fmax(red[z][threadIdx.x], red[z][threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) {
+        unsigned long long *ext = reinterpret_cast<unsigned long long *>(status) + STATUS_EXT;
+        atomicMax(&ext[threadIdx.x], (unsigned long long)__double_as_longlong(red[threadIdx.x][0]));
+    }
 }
 
 __global__ void k_zero_outputs(double *loglik, double *grad)
@@ -269,16 +318,41 @@ __global__ __launch_bounds__(256) void k_stage_f32(const double *__restrict__ t,
                                                    float *__restrict__ rh, float *__restrict__ rl,
                                                    float *__restrict__ vh, float *__restrict__ vl,
                                                    float *__restrict__ dl, float *__restrict__ uh,
-                                                   float *__restrict__ ul)
+                                                   float *__restrict__ ul, int *status, int *__restrict__ xi,
+                                                   int *__restrict__ yi, int *__restrict__ ti)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n_pad)
         return;
+    // fixed-point quantum q = 2^-k of the scaled coordinates: every |coordinate| / q
+    // stays within 2^29, so differences fit int32; k <= 20 keeps every time
+    // difference that can give a nonzero background term (|dt'| < 16) exact in FP32
+    double q = 1.0, q2 = 1.0;
+    if (HAWKES_IGEOM) {
+        const unsigned long long *ext = reinterpret_cast<const unsigned long long *>(status) + STATUS_EXT;
+        const double mxy = fmax(__longlong_as_double((long long)ext[0]), __longlong_as_double((long long)ext[1]));
+        const double m = fmax(mxy * c.sx, __longlong_as_double((long long)ext[2]) * c.st);
+        int e = 0;
+        frexp(m, &e);  // m < 2^e
+        const int k = (29 - e < 20) ? 29 - e : 20;
+        q = ldexp(1.0, -k);
+        q2 = q * q;
+        if (i == 0) {
+            double *geo = reinterpret_cast<double *>(status) + STATUS_GEO;
+            geo[0] = q;
+            geo[1] = q2;
+        }
+    }
     if (i >= n) {
         xs[i] = PAD_COORD;
         ys[i] = PAD_COORD;
         tsd[i] = 0.0;
         rh[i] = rl[i] = vh[i] = vl[i] = dl[i] = uh[i] = ul[i] = 0.0f;
+        if (HAWKES_IGEOM) {
+            // padding sources sit at least 2^29 quanta (>= 512 scaled units) from every event
+            xi[i] = yi[i] = -(1 << 30);
+            ti[i] = 0;
+        }
         return;
     }
     const int64_t k = i / TS;
@@ -289,8 +363,14 @@ __global__ __launch_bounds__(256) void k_stage_f32(const double *__restrict__ t,
     xs[i] = x[i] * c.sx;
     ys[i] = y[i] * c.sx;
     tsd[i] = t[i] * c.st;
+    if (HAWKES_IGEOM) {
+        xi[i] = int(rint(x[i] * c.sx / q));
+        yi[i] = int(rint(y[i] * c.sx / q));
+        ti[i] = int(rint(t[i] * c.st / q));
+    }
     float hi, lo;
-    split_f32(u * c.rr, hi, lo);
+    // the triggering exponent scale takes the quantum's square (a power of two: exact)
+    split_f32(u * c.rr * q2, hi, lo);
     rh[i] = hi;
     rl[i] = lo;
     split_f32(u * exp(-c.omega * d), hi, lo);
@@ -318,7 +398,50 @@ struct PairF32 {
     // only.  Without skipping, skip_gap is infinite and window = 0.
     double skip_gap;
     int window;
+    // integer geometry (HAWKES_IGEOM): fixed-point coordinates and {q, q^2}
+    const int *xi, *yi, *ti;
+    const double *geo;
 };
+
+// Pair geometry: the scaled squared distance D and the background exponent
+// A = D + dt'^2 in FP32, and the scaled time difference in FP64.
+//  FP64 coordinates: differences and squares in FP64, D and A each rounded once.
+//  int32 fixed-point coordinates (units of q): exact differences, each rounded
+//  once to FP32 (times exactly wherever the background term can be nonzero);
+//  D and A come out in units of q^2.
+__device__ inline void geom_da(double xn, double yn, double tn, double xm, double ym, double tm, float &D, float &A)
+{
+    const double dx = xn - xm, dy = yn - ym, dt = tn - tm;
+    const double d2 = fma(dy, dy, dx * dx);
+    D = float(d2);
+    A = float(fma(dt, dt, d2));
+}
+__device__ inline void geom_da(int xn, int yn, int tn, int xm, int ym, int tm, float &D, float &A)
+{
+    const float dx = float(xn - xm), dy = float(yn - ym), dt = float(tn - tm);
+    D = fmaf(dy, dy, dx * dx);
+    A = fmaf(dt, dt, D);
+}
+__device__ inline float geom_d(double xn, double yn, double xm, double ym)
+{
+    const double dx = xn - xm, dy = yn - ym;
+    return float(fma(dy, dy, dx * dx));
+}
+__device__ inline float geom_d(int xn, int yn, int xm, int ym)
+{
+    const float dx = float(xn - xm), dy = float(yn - ym);
+    return fmaf(dy, dy, dx * dx);
+}
+__device__ inline double geom_dt(double tn, double tm, double) { return tn - tm; }
+__device__ inline double geom_dt(int tn, int tm, double q) { return double(tn - tm) * q; }
+
+#if HAWKES_IGEOM
+typedef int coord_t;
+#define HK_BG_ARG(A) ((A) * q2f)  // D and A in units of q^2
+#else
+typedef double coord_t;
+#define HK_BG_ARG(A) (A)
+#endif
 
 // The FP32 fused sweep.  GRAD = false keeps only S0 and G0 (log-likelihood).
 //
@@ -342,11 +465,20 @@ struct PairF32 {
 template <bool GRAD>
 __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
 {
-    __shared__ double lx[2][TS], ly[2][TS], lt[2][TS];
+    __shared__ coord_t lx[2][TS], ly[2][TS], lt[2][TS];
     __shared__ float lrh[2][TS], lrl[2][TS], lvh[2][TS], lvl[2][TS], ld[2][TS], luh[2][TS], lul[2][TS];
     __shared__ int lg[2][TS];
 
     const int tid = threadIdx.x;
+#if HAWKES_IGEOM
+    const coord_t *cx = a.xi, *cy = a.yi, *ct = a.ti;
+    const double qnt = a.geo[0], qnt2 = a.geo[1];
+#else
+    const coord_t *cx = a.xs, *cy = a.ys, *ct = a.tsd;
+    const double qnt = 1.0, qnt2 = 1.0;
+#endif
+    const float q2f = float(qnt2);
+    (void)q2f;
     const int64_t tbr = blockIdx.x / a.num_chunks;
     const int64_t chunk = blockIdx.x - tbr * a.num_chunks;
     const int64_t tb = a.num_tb - 1 - tbr;  // latest (most expensive) target blocks first
@@ -354,16 +486,17 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
     const int64_t iend = (i0 + TB < a.row_end) ? i0 + TB : a.row_end;
     const double t_lo = a.t[i0], t_hi = a.t[iend - 1];
 
-    double xn[KT], yn[KT], tsn[KT], trn[KT];
+    coord_t xn[KT], yn[KT], tsn[KT];
+    double trn[KT];
     int gn[KT];
 #pragma unroll
     for (int q = 0; q < KT; ++q) {
         int64_t i = i0 + tid + q * WG;
         if (i >= iend)
             i = iend - 1;
-        xn[q] = a.xs[i];
-        yn[q] = a.ys[i];
-        tsn[q] = a.tsd[i];
+        xn[q] = cx[i];
+        yn[q] = cy[i];
+        tsn[q] = ct[i];
         trn[q] = a.t[i];
         gn[q] = a.g[i];
     }
@@ -393,13 +526,13 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
     const int64_t k1 = (k0 + chunk_tiles < k_end) ? k0 + chunk_tiles : k_end;
 
     struct Rec {
-        double x, y, t;
+        coord_t x, y, t;
         float rh, rl, vh, vl, d, uh, ul;
         int g;
     };
     auto fetch = [&](int64_t k) {
         const int64_t j = k * TS + tid;
-        return Rec{a.xs[j], a.ys[j], a.tsd[j], a.rh[j], a.rl[j], a.vh[j], a.vl[j], a.dl[j], a.uh[j], a.ul[j], a.g[j]};
+        return Rec{cx[j], cy[j], ct[j], a.rh[j], a.rl[j], a.vh[j], a.vl[j], a.dl[j], a.uh[j], a.ul[j], a.g[j]};
     };
     auto store = [&](const Rec &r, int buf) {
         lx[buf][tid] = r.x;
@@ -443,9 +576,9 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
         for (int q = 0; q < KT; ++q)
             gt[q][0] = gt[q][1] = gt[q][2] = 0.0;
 
-        const double *sx = lx[buf];
-        const double *sy = ly[buf];
-        const double *st = lt[buf];
+        const coord_t *sx = lx[buf];
+        const coord_t *sy = ly[buf];
+        const coord_t *st = lt[buf];
 
         if (cls != MIXED) {
             const bool causal = (cls == CAUSAL);
@@ -461,12 +594,11 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
                     HK_UNROLL(HAWKES_UJ)
                     for (int j = 0; j < GS; ++j) {
                         const int m = m0 + j;
-                        const double xm = sx[m], ym = sy[m];
+                        const coord_t xm = sx[m], ym = sy[m];
                         const float rhm = srh[m], rlm = srl[m], vhm = svh[m], vlm = svl[m], dm = sd[m];
 #pragma unroll
                         for (int q = 0; q < KT; ++q) {
-                            const double dx = xn[q] - xm, dy = yn[q] - ym;
-                            const float D = float(fma(dy, dy, dx * dx));
+                            const float D = geom_d(xn[q], yn[q], xm, ym);
                             const float t1 = fmaf(rlm, D, rhm * D);
                             const float E = __builtin_amdgcn_exp2f(-t1);
                             const float p = fmaf(vlm, E, vhm * E);
@@ -481,15 +613,13 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
                     HK_UNROLL(HAWKES_UJ)
                     for (int j = 0; j < GS; ++j) {
                         const int m = m0 + j;
-                        const double xm = sx[m], ym = sy[m], tm = st[m];
+                        const coord_t xm = sx[m], ym = sy[m], tm = st[m];
                         const float rhm = srh[m], rlm = srl[m], vhm = svh[m], vlm = svl[m], dm = sd[m];
 #pragma unroll
                         for (int q = 0; q < KT; ++q) {
-                            const double dx = xn[q] - xm, dy = yn[q] - ym, dt = tsn[q] - tm;
-                            const double d2 = fma(dy, dy, dx * dx);
-                            const float D = float(d2);
-                            const float A = float(fma(dt, dt, d2));
-                            const float b = __builtin_amdgcn_exp2f(-A);
+                            float D, A;
+                            geom_da(xn[q], yn[q], tsn[q], xm, ym, tm, D, A);
+                            const float b = __builtin_amdgcn_exp2f(-HK_BG_ARG(A));
                             const float t1 = fmaf(rlm, D, rhm * D);
                             const float E = __builtin_amdgcn_exp2f(-t1);
                             const float p = fmaf(vlm, E, vhm * E);
@@ -507,16 +637,14 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
                     HK_UNROLL(HAWKES_UJ)
                     for (int j = 0; j < GS; ++j) {
                         const int m = m0 + j;
-                        const double xm = sx[m], ym = sy[m], tm = st[m];
+                        const coord_t xm = sx[m], ym = sy[m], tm = st[m];
 #pragma unroll
                         for (int q = 0; q < KT; ++q) {
-                            const double dx = xn[q] - xm, dy = yn[q] - ym, dt = tsn[q] - tm;
-                            const double d2 = fma(dy, dy, dx * dx);
-                            const float A = float(fma(dt, dt, d2));
-                            const float b = __builtin_amdgcn_exp2f(-A);
+                            float D, A;
+                            geom_da(xn[q], yn[q], tsn[q], xm, ym, tm, D, A);
+                            const float b = __builtin_amdgcn_exp2f(-HK_BG_ARG(A));
                             f[q][0] += b;
                             if (GRAD) {
-                                const float D = float(d2);
                                 f[q][1] = fmaf(b, D, f[q][1]);
                                 f[q][2] = fmaf(b, A, f[q][2]);
                             }
@@ -567,16 +695,15 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
                         f[q][z] = 0.0f;
                 for (int j = 0; j < GS; ++j) {
                     const int m = m0 + j;
-                    const double xm = sx[m], ym = sy[m], tm = st[m];
+                    const coord_t xm = sx[m], ym = sy[m], tm = st[m];
                     const float rhm = srh[m], rlm = srl[m], uhm = suh[m], ulm = sul[m];
                     const int gm = sg[m];
 #pragma unroll
                     for (int q = 0; q < KT; ++q) {
-                        const double dx = xn[q] - xm, dy = yn[q] - ym, dt = tsn[q] - tm;
-                        const double d2 = fma(dy, dy, dx * dx);
-                        const float D = float(d2);
-                        const float A = float(fma(dt, dt, d2));
-                        float b = __builtin_amdgcn_exp2f(-A);
+                        float D, A;
+                        geom_da(xn[q], yn[q], tsn[q], xm, ym, tm, D, A);
+                        const double dt = geom_dt(tsn[q], tm, qnt);
+                        float b = __builtin_amdgcn_exp2f(-HK_BG_ARG(A));
                         b = (gm != gn[q]) ? b : 0.0f;
                         const float t1 = fmaf(rlm, D, rhm * D);
                         const float arg = float(fma(a.w2, dt, double(t1)));
@@ -625,8 +752,8 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
         out[0 * stride + rr] = acc[q][0] * ce;
         out[3 * stride + rr] = acc[q][3] * ce;
         if (GRAD) {
-            out[1 * stride + rr] = acc[q][1] * (a.out_s1 * ce);
-            out[2 * stride + rr] = (acc[q][2] - acc[q][1]) * (a.out_s2 * ce);
+            out[1 * stride + rr] = acc[q][1] * (a.out_s1 * qnt2 * ce);
+            out[2 * stride + rr] = (acc[q][2] - acc[q][1]) * (a.out_s2 * qnt2 * ce);
             out[4 * stride + rr] = acc[q][4] * (a.out_g1 * ce);
             out[5 * stride + rr] = acc[q][5] * ce;
         }
@@ -1104,8 +1231,17 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
         float *rh = at<float>(ws, L.rh), *rl = at<float>(ws, L.rl), *vh = at<float>(ws, L.vh);
         float *vl = at<float>(ws, L.vl), *dl = at<float>(ws, L.dl), *uh = at<float>(ws, L.uh);
         float *ul = at<float>(ws, L.ul);
+        int *xi = HAWKES_IGEOM ? at<int>(ws, L.xi) : nullptr;
+        int *yi = HAWKES_IGEOM ? at<int>(ws, L.yi) : nullptr;
+        int *ti = HAWKES_IGEOM ? at<int>(ws, L.ti) : nullptr;
+        if (HAWKES_IGEOM) {
+            hipLaunchKernelGGL(k_extent, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, stream, ev->t, ev->x, ev->y,
+                               n, status);
+            if ((rc = check_launch("extent")) != HAWKES_OK)
+                return rc;
+        }
         hipLaunchKernelGGL(k_stage_f32, dim3(stage_blocks), dim3(256), 0, stream, ev->t, ev->x, ev->y, ev->s, n,
-                           L.n_pad, sc, tile, xs, ys, tsd, rh, rl, vh, vl, dl, uh, ul);
+                           L.n_pad, sc, tile, xs, ys, tsd, rh, rl, vh, vl, dl, uh, ul, status, xi, yi, ti);
         if ((rc = check_launch("stage_f32")) != HAWKES_OK)
             return rc;
         PairF32 a;
@@ -1145,6 +1281,10 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
             a.skip_gap = HUGE_VAL;
             a.window = 0;
         }
+        a.xi = xi;
+        a.yi = yi;
+        a.ti = ti;
+        a.geo = reinterpret_cast<const double *>(status) + STATUS_GEO;
         if (g_timing && (rc = record_event(g_ev_start, stream)) != HAWKES_OK)
             return rc;
         if (grad)

@@ -90,6 +90,12 @@ class SurrogateNet:
                    "hawkes_mlp_adam_step")
 
 
+def group_means(v: np.ndarray, groups: np.ndarray) -> np.ndarray:
+    """Mean of v over each group id 0..max(groups)."""
+    n = int(groups.max()) + 1
+    return np.bincount(groups, weights=v, minlength=n) / np.maximum(np.bincount(groups, minlength=n), 1)
+
+
 @dataclass
 class Standardiser:
     """Affine maps between log theta / l / gradient and the network's units."""
@@ -100,9 +106,12 @@ class Standardiser:
     s_y: float
 
     @classmethod
-    def fit(cls, logtheta: np.ndarray, ll: np.ndarray) -> "Standardiser":
+    def fit(cls, logtheta: np.ndarray, ll: np.ndarray, groups: np.ndarray | None = None) -> "Standardiser":
+        """With ``groups`` (tuples that share one latent-location draw), the value scale is the
+        spread of l within the groups: the offset a draw adds to l is not part of the fit."""
         s_z = np.maximum(logtheta.std(axis=0), 1e-12)
-        return cls(logtheta.mean(axis=0), s_z, float(ll.mean()), float(max(ll.std(), 1e-12)))
+        spread = ll if groups is None else ll - group_means(ll, groups)[groups]
+        return cls(logtheta.mean(axis=0), s_z, float(ll.mean()), float(max(spread.std(), 1e-12)))
 
     def z(self, logtheta):
         return (np.asarray(logtheta) - self.m_z) / self.s_z
@@ -136,17 +145,30 @@ class Surrogate:
 
 
 def train(net: SurrogateNet, std: Standardiser, logtheta, ll, grad_logtheta, *, lam=1.0, epochs=40, batch=256,
-          lr=1e-3, seed=0, lr_decay=0.98, log=None):
-    """Adam on the Sobolev loss over the tuples; returns the per-epoch mean loss."""
+          lr=1e-3, seed=0, lr_decay=0.98, log=None, groups: np.ndarray | None = None):
+    """Adam on the Sobolev loss over the tuples; returns the per-epoch mean loss.
+
+    With ``groups`` (one id per tuple: the latent-location draw it was computed under, ids
+    0..G-1), the value term fits l only up to one offset per group: each epoch the targets are
+    l - mean_group(l) + mean_group(f) with f the current network, so that the value residual of
+    a tuple is its residual minus its group's mean residual.  The gradient term is unchanged."""
     Z = torch.tensor(std.z(logtheta), dtype=torch.float32, device=net.device)
     Y = torch.tensor(std.y(ll), dtype=torch.float32, device=net.device)
     G = torch.tensor(std.g(grad_logtheta), dtype=torch.float32, device=net.device)
     n = Z.shape[0]
+    if groups is not None:
+        groups = np.asarray(groups, dtype=np.int64)
+        yc = std.y(ll)
+        yc = yc - group_means(yc, groups)[groups]
     rng = np.random.default_rng(seed)
     grad = torch.empty(P, dtype=torch.float32, device=net.device)
     step = 0
     history = []
     for ep in range(epochs):
+        if groups is not None:
+            f = np.concatenate([net.forward(Z[i:i + 4096], want_grad=False)[0].cpu().numpy()
+                                for i in range(0, n, 4096)]).astype(np.float64)
+            Y = torch.tensor(yc + group_means(f, groups)[groups], dtype=torch.float32, device=net.device)
         perm = torch.from_numpy(rng.permutation(n)).to(net.device)
         tot = torch.zeros(1, dtype=torch.float32, device=net.device)
         nb = 0

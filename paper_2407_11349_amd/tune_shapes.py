@@ -5,8 +5,8 @@ HAWKES_KT (target rows per lane), HAWKES_UJ (unroll of the source loop),
 HAWKES_GS (FP32 terms per FP64 fold) and HAWKES_WAVES_PER_EU (register
 budget), into paper_2407_11349_amd/_variants/.  Every shape is timed with the
 library's own HIP-event hook on the 1e6-event, 1200-day workload (FP32
-log-likelihood + gradient, and the FP32 skip mode), and its result is
-compared with the first shape's.
+log-likelihood + gradient, and the FP32 skip mode); its result is compared
+with the first shape's and with the stored FP64 oracle value of that workload.
 
     python -m paper_2407_11349_amd.tune_shapes build [shape ...]
     python -m paper_2407_11349_amd.tune_shapes time [--n N] [shape ...]
@@ -37,6 +37,12 @@ SHAPES = {
     "kt2_uj2_w4": {"HAWKES_KT": 2, "HAWKES_UJ": 2, "HAWKES_WAVES_PER_EU": 4},
     "kt4_nowpe": {"HAWKES_KT": 4, "HAWKES_WAVES_PER_EU": 0},
     "kt4_w3": {"HAWKES_KT": 4, "HAWKES_WAVES_PER_EU": 3},
+    "kt2_gs16": {"HAWKES_KT": 2, "HAWKES_GS": 16, "HAWKES_UJ": 8},
+    # exact int32 differences of fixed-point coordinates instead of FP64 differences
+    "kt2_ig": {"HAWKES_KT": 2, "HAWKES_IGEOM": 1},
+    "kt2_ig_gs16": {"HAWKES_KT": 2, "HAWKES_IGEOM": 1, "HAWKES_GS": 16, "HAWKES_UJ": 8},
+    "kt4_ig": {"HAWKES_KT": 4, "HAWKES_IGEOM": 1},
+    "kt2_ig_w4": {"HAWKES_KT": 2, "HAWKES_IGEOM": 1, "HAWKES_WAVES_PER_EU": 4},
 }
 
 
@@ -81,6 +87,12 @@ def time_shapes(names, n: int) -> None:
     th = synth.theta_default()
     dev = hk.DeviceEvents.from_arrays(ev.t, ev.x, ev.y, ev.s)
     ref = None
+    gold = None
+    gpath = ROOT / "tests" / "golden" / "oracle_values.json"
+    if n == 1_000_000 and gpath.exists():
+        import json
+
+        gold = json.load(open(gpath)).get("n1m")
     for name in names:
         _lib._lib = None
         lib = _lib.load(OUT / f"libhawkes_{name}.so")
@@ -101,7 +113,13 @@ def time_shapes(names, n: int) -> None:
             hk.loglik_grad(dev, th, "fp32_skip", ws=wss)
             torch.cuda.synchronize()
             skip_ms = hk.last_pair_kernel_ms()
-            print(f"| {name} | {wgs} | {min(ms):.1f} | {skip_ms:.1f} | {dl:.1e} | {dg:.1e} |", flush=True)
+            if gold is not None:
+                el = abs(llv - gold["loglik"]) / abs(gold["loglik"])
+                eg = float(np.max(np.abs(gv - np.array(gold["grad"])) / np.abs(np.array(gold["grad"]))))
+                err = f" {el:.1e} | {eg:.1e} |"
+            else:
+                err = " - | - |"
+            print(f"| {name} | {wgs} | {min(ms):.1f} | {skip_ms:.1f} | {dl:.1e} | {dg:.1e} |{err}", flush=True)
             del ws, wss
         hk.set_timing(False)
         lib.hawkes_tune_target_workgroups(32768)
@@ -120,8 +138,9 @@ def main() -> None:
     if a.what == "build":
         build(names)
     else:
-        print("| shape | target workgroups | FP32 ms (best of 3) | FP32 skip ms | loglik rel diff | grad rel diff |")
-        print("|---|---|---|---|---|---|")
+        print("| shape | target workgroups | FP32 ms (best of 3) | FP32 skip ms | loglik rel diff | grad rel diff "
+              "| loglik rel err vs oracle | grad rel err vs oracle |")
+        print("|---|---|---|---|---|---|---|---|")
         time_shapes(names, a.n)
 
 

@@ -101,3 +101,44 @@ def test_training_fits_a_smooth_six_dimensional_function():
     yt, gt = yv[5000:], gv[5000:]
     assert np.sqrt(np.mean((yh - yt) ** 2)) < 0.05 * yt.std()
     assert np.sqrt(np.mean((gh - gt) ** 2)) < 0.1 * gt.std()
+
+
+def test_training_up_to_one_offset_per_group():
+    """Tuples in groups of 21, each group's values shifted by a large random offset (as a
+    latent-location draw shifts the log-likelihood): trained with the groups, the network
+    fits the function up to per-group offsets, and better than trained without them."""
+    from paper_2407_11349_amd.surrogate import group_means
+
+    rng = np.random.default_rng(9)
+    A = rng.normal(size=(6, 6))
+    Q = A @ A.T / 6 + np.eye(6)
+
+    def target(x):
+        return -0.5 * np.einsum("bi,ij,bj->b", x, Q, x), -(x @ Q)
+
+    n_groups, per = 300, 21
+    x = rng.normal(size=(n_groups * per, 6)) * 0.5
+    groups = np.repeat(np.arange(n_groups), per)
+    yv, gv = target(x)
+    offsets = rng.normal(size=n_groups) * 30.0
+    yn = yv + offsets[groups]
+    tr = groups < 270
+    te = ~tr
+
+    def within_rmse(net, std):
+        yh, _ = Surrogate(net, std).value_and_grad(x[te])
+        e = yh - yv[te]
+        g = groups[te] - 270
+        return np.sqrt(np.mean((e - group_means(e, g)[g]) ** 2))
+
+    spread = np.sqrt(np.mean((yv[te] - group_means(yv[te], groups[te] - 270)[groups[te] - 270]) ** 2))
+    std_g = Standardiser.fit(x[tr], yn[tr], groups[tr])
+    net_g = SurrogateNet(init_params(21))
+    train(net_g, std_g, x[tr], yn[tr], gv[tr], lam=1.0, epochs=30, batch=256, lr=2e-3, seed=2, groups=groups[tr])
+    std_p = Standardiser.fit(x[tr], yn[tr])
+    net_p = SurrogateNet(init_params(21))
+    train(net_p, std_p, x[tr], yn[tr], gv[tr], lam=1.0, epochs=30, batch=256, lr=2e-3, seed=2)
+    e_g, e_p = within_rmse(net_g, std_g), within_rmse(net_p, std_p)
+    print(f"within-group rmse: grouped {e_g:.3f}, plain {e_p:.3f}, spread {spread:.3f}", flush=True)
+    assert e_g < 0.1 * spread
+    assert e_g < e_p
