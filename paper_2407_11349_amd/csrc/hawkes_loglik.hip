@@ -80,6 +80,12 @@ namespace {
 #ifndef HAWKES_IGEOM
 #define HAWKES_IGEOM 0
 #endif
+// Source records: 0 = staged through LDS (double-buffered, a barrier per
+// tile); 1 = read by every wave straight from global memory with
+// wave-uniform (scalar) loads, no LDS and no barriers.
+#ifndef HAWKES_SMEM
+#define HAWKES_SMEM 0
+#endif
 #define HK_STR(x) #x
 #define HK_UNROLL(n) _Pragma(HK_STR(unroll n))
 
@@ -465,9 +471,11 @@ typedef double coord_t;
 template <bool GRAD>
 __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
 {
+#if !HAWKES_SMEM
     __shared__ coord_t lx[2][TS], ly[2][TS], lt[2][TS];
     __shared__ float lrh[2][TS], lrl[2][TS], lvh[2][TS], lvl[2][TS], ld[2][TS], luh[2][TS], lul[2][TS];
     __shared__ int lg[2][TS];
+#endif
 
     const int tid = threadIdx.x;
 #if HAWKES_IGEOM
@@ -525,6 +533,7 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
     const int64_t k0 = chunk * chunk_tiles;
     const int64_t k1 = (k0 + chunk_tiles < k_end) ? k0 + chunk_tiles : k_end;
 
+#if !HAWKES_SMEM
     struct Rec {
         coord_t x, y, t;
         float rh, rl, vh, vl, d, uh, ul;
@@ -547,17 +556,22 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
         lul[buf][tid] = r.ul;
         lg[buf][tid] = r.g;
     };
+#endif
 
+#if !HAWKES_SMEM
     if (k0 < k1)
         store(fetch(k0), 0);
     __syncthreads();
+#endif
 
     for (int64_t k = k0; k < k1; ++k) {
+#if !HAWKES_SMEM
         const int buf = int(k - k0) & 1;
         const bool more = (k + 1 < k1);
         Rec nxt{};
         if (more)
             nxt = fetch(k + 1);  // global loads in flight while this tile is swept
+#endif
 
         const double first = a.tile[3 * k + 0], last = a.tile[3 * k + 1];
         const int cls = (last < t_lo) ? CAUSAL : ((first > t_hi) ? ANTI : MIXED);
@@ -576,13 +590,26 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
         for (int q = 0; q < KT; ++q)
             gt[q][0] = gt[q][1] = gt[q][2] = 0.0;
 
+#if !HAWKES_SMEM
         const coord_t *sx = lx[buf];
         const coord_t *sy = ly[buf];
         const coord_t *st = lt[buf];
+        const float *lrh_ = lrh[buf], *lrl_ = lrl[buf], *lvh_ = lvh[buf], *lvl_ = lvl[buf], *ld_ = ld[buf];
+        const float *luh_ = luh[buf], *lul_ = lul[buf];
+        const int *lg_ = lg[buf];
+#else
+        const int64_t j0 = k * TS;
+        const coord_t *sx = cx + j0;
+        const coord_t *sy = cy + j0;
+        const coord_t *st = ct + j0;
+        const float *lrh_ = a.rh + j0, *lrl_ = a.rl + j0, *lvh_ = a.vh + j0, *lvl_ = a.vl + j0, *ld_ = a.dl + j0;
+        const float *luh_ = a.uh + j0, *lul_ = a.ul + j0;
+        const int *lg_ = a.g + j0;
+#endif
 
         if (cls != MIXED) {
             const bool causal = (cls == CAUSAL);
-            const float *srh = lrh[buf], *srl = lrl[buf], *svh = lvh[buf], *svl = lvl[buf], *sd = ld[buf];
+            const float *srh = lrh_, *srl = lrl_, *svh = lvh_, *svl = lvl_, *sd = ld_;
             for (int m0 = 0; m0 < TS; m0 += GS) {
                 float f[KT][6];
 #pragma unroll
@@ -684,8 +711,8 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
         } else {
             // tiles overlapping the block's time range: per-pair tie-group
             // masks and the triggering time factor formed per pair in FP64
-            const float *srh = lrh[buf], *srl = lrl[buf], *suh = luh[buf], *sul = lul[buf];
-            const int *sg = lg[buf];
+            const float *srh = lrh_, *srl = lrl_, *suh = luh_, *sul = lul_;
+            const int *sg = lg_;
             for (int m0 = 0; m0 < TS; m0 += GS) {
                 float f[KT][6];
 #pragma unroll
@@ -734,9 +761,11 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
             }
         }
 
+#if !HAWKES_SMEM
         if (more)
             store(nxt, buf ^ 1);
         __syncthreads();
+#endif
     }
 
     // write this chunk's sums in the natural units of the six sums

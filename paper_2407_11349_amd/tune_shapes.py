@@ -43,6 +43,13 @@ SHAPES = {
     "kt2_ig_gs16": {"HAWKES_KT": 2, "HAWKES_IGEOM": 1, "HAWKES_GS": 16, "HAWKES_UJ": 8},
     "kt4_ig": {"HAWKES_KT": 4, "HAWKES_IGEOM": 1},
     "kt2_ig_w4": {"HAWKES_KT": 2, "HAWKES_IGEOM": 1, "HAWKES_WAVES_PER_EU": 4},
+    # source records through wave-uniform scalar loads instead of LDS tiles
+    "kt2_smem": {"HAWKES_KT": 2, "HAWKES_SMEM": 1},
+    "kt4_smem": {"HAWKES_KT": 4, "HAWKES_SMEM": 1},
+    "kt2_smem_w4": {"HAWKES_KT": 2, "HAWKES_SMEM": 1, "HAWKES_WAVES_PER_EU": 4},
+    "kt2_smem_uj4": {"HAWKES_KT": 2, "HAWKES_SMEM": 1, "HAWKES_UJ": 4},
+    "kt4_smem_uj4": {"HAWKES_KT": 4, "HAWKES_SMEM": 1, "HAWKES_UJ": 4},
+    "kt2_smem_ig": {"HAWKES_KT": 2, "HAWKES_SMEM": 1, "HAWKES_IGEOM": 1},
 }
 
 
