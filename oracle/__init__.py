@@ -45,11 +45,11 @@ def _load():
         build()
         lib = ctypes.CDLL(str(_LIB))
         dp = ctypes.POINTER(ctypes.c_double)
-        lib.hawkes_oracle_loglik.argtypes = [ctypes.c_int64, dp, dp, dp, dp, dp, ctypes.c_int64,
+        lib.hawkes_oracle_loglik.argtypes = [ctypes.c_int64, dp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int64,
                                              ctypes.c_int64, dp, dp, dp, dp, dp]
         lib.hawkes_oracle_loglik.restype = ctypes.c_int
-        lib.hawkes_oracle_rate_parts.argtypes = [ctypes.c_int64, dp, dp, dp, dp, dp, ctypes.c_int64,
-                                                 ctypes.c_int64, dp, dp]
+        lib.hawkes_oracle_rate_parts.argtypes = [ctypes.c_int64, dp, dp, dp, dp, dp, ctypes.c_double,
+                                                 ctypes.c_int64, ctypes.c_int64, dp, dp]
         lib.hawkes_oracle_rate_parts.restype = ctypes.c_int
         u64p = ctypes.POINTER(ctypes.c_uint64)
         lib.hawkes_oracle_philox4x64_10.argtypes = [u64p, u64p, u64p]
@@ -69,10 +69,12 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def loglik(t, x, y, s, theta, rows=None, per_row=False):
+def loglik(t, x, y, s, theta, rows=None, per_row=False, area=0.0):
     """Log-likelihood of rows [r0, r1) (default all), its 6-gradient, optional per-row terms.
 
-    Returns (loglik, grad) or, with per_row=True, (loglik, grad, lam, Lam, ell).
+    area = 0: Gaussian spatial background N2(.; tau_x^2); area > 0: the paper's spatially
+    uniform background 1/area.  Returns (loglik, grad) or, with per_row=True,
+    (loglik, grad, lam, Lam, ell).
     """
     lib = _load()
     t, x, y, s, th = _f64(t), _f64(x), _f64(y), _f64(s), _f64(theta)
@@ -84,8 +86,8 @@ def loglik(t, x, y, s, theta, rows=None, per_row=False):
     lam = np.zeros(nr) if per_row else None
     comp = np.zeros(nr) if per_row else None
     ell = np.zeros(nr) if per_row else None
-    rc = lib.hawkes_oracle_loglik(n, _dp(t), _dp(x), _dp(y), _dp(s), _dp(th), r0, r1, _dp(ll), _dp(g),
-                                  _dp(lam), _dp(comp), _dp(ell))
+    rc = lib.hawkes_oracle_loglik(n, _dp(t), _dp(x), _dp(y), _dp(s), _dp(th), float(area), r0, r1, _dp(ll),
+                                  _dp(g), _dp(lam), _dp(comp), _dp(ell))
     if rc != 0:
         raise ValueError("oracle rejected its arguments")
     if per_row:
@@ -93,7 +95,7 @@ def loglik(t, x, y, s, theta, rows=None, per_row=False):
     return float(ll[0]), g
 
 
-def rate_parts(t, x, y, s, theta, rows=None):
+def rate_parts(t, x, y, s, theta, rows=None, area=0.0):
     """(bg, tr): background and triggering sums of lambda_n without mu and xi."""
     lib = _load()
     t, x, y, s, th = _f64(t), _f64(x), _f64(y), _f64(s), _f64(theta)
@@ -101,7 +103,8 @@ def rate_parts(t, x, y, s, theta, rows=None):
     r0, r1 = (0, n) if rows is None else rows
     bg = np.zeros(r1 - r0)
     tr = np.zeros(r1 - r0)
-    if lib.hawkes_oracle_rate_parts(n, _dp(t), _dp(x), _dp(y), _dp(s), _dp(th), r0, r1, _dp(bg), _dp(tr)):
+    if lib.hawkes_oracle_rate_parts(n, _dp(t), _dp(x), _dp(y), _dp(s), _dp(th), float(area), r0, r1, _dp(bg),
+                                    _dp(tr)):
         raise ValueError("oracle rejected its arguments")
     return bg, tr
 

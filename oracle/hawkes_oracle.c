@@ -25,7 +25,10 @@
  *   l   = sum_n l_n
  *
  * The background carries the spatial Gaussian N2(.; tau_x^2) (six parameters
- * theta = (mu, tau_x, tau_t, xi, h0, omega)); self pairs and exact time ties
+ * theta = (mu, tau_x, tau_t, xi, h0, omega)), or, when a spatial-domain area
+ * A > 0 is given, the spatially uniform density 1/A of the paper's own models
+ * (equation "fixed": mu0 / A(X) times the temporal Gaussian; tau_x then plays
+ * no part and its derivative is 0); self pairs and exact time ties
  * are excluded from both sums, as the indicator in equation "fixed" and the
  * appendix kernel's time tests do.  Gradients are the term-by-term partial
  * derivatives of the definition above with respect to theta; a floored event
@@ -84,7 +87,7 @@ enum { P_MU = 0, P_TAUX = 1, P_TAUT = 2, P_XI = 3, P_H0 = 4, P_OMEGA = 5 };
  * out[0] = lambda_n, out[1 + k] = d lambda_n / d theta_k.
  */
 static void oracle_rate(int64_t nt, int64_t n, const double *t, const double *x, const double *y,
-                        const double *s, const double *th, double *out)
+                        const double *s, const double *th, double area, double *out)
 {
     const double mu = th[P_MU], taux = th[P_TAUX], taut = th[P_TAUT];
     const double xi = th[P_XI], h0 = th[P_H0], omega = th[P_OMEGA];
@@ -98,11 +101,19 @@ static void oracle_rate(int64_t nt, int64_t n, const double *t, const double *x,
         const double d2 = dx * dx + dy * dy;
 
         /* background pair term and its derivatives */
+        if (area > 0.0) {
+            /* spatially uniform background: 1/A times the temporal Gaussian */
+            const double beta = n1_density(dt, taut * taut) / area;
+            nm_add(&acc[0], mu * beta);
+            nm_add(&acc[1 + P_MU], beta);
+            nm_add(&acc[1 + P_TAUT], mu * beta * (dt * dt / (taut * taut * taut) - 1.0 / taut));
+        } else {
         const double beta = n2_density(d2, taux * taux) * n1_density(dt, taut * taut);
         nm_add(&acc[0], mu * beta);
         nm_add(&acc[1 + P_MU], beta);
         nm_add(&acc[1 + P_TAUX], mu * beta * (d2 / (taux * taux * taux) - 2.0 / taux));
         nm_add(&acc[1 + P_TAUT], mu * beta * (dt * dt / (taut * taut * taut) - 1.0 / taut));
+        }
 
         if (t[m] < tn) {
             /* triggering pair term: source m's spatial sd is h0 * s_m */
@@ -141,6 +152,7 @@ static void oracle_compensator(double tm, double tN, const double *th, double *o
  *   n            number of events (>= 1); t need not be sorted
  *   t, x, y, s   host arrays of length n (days, km, km, bandwidth scale > 0)
  *   theta        (mu, tau_x, tau_t, xi, h0, omega), all > 0
+ *   area         0: Gaussian spatial background; > 0: uniform background 1/area (km^2)
  *   loglik       out: sum of l_n over the rows
  *   grad         out (6) or NULL: gradient of that sum with respect to theta
  *   lam, comp    out (row_end - row_begin) or NULL: lambda_n and Lambda_n
@@ -149,10 +161,10 @@ static void oracle_compensator(double tm, double tN, const double *th, double *o
  * Returns 0, or -1 on invalid arguments.
  */
 int hawkes_oracle_loglik(int64_t n, const double *t, const double *x, const double *y, const double *s,
-                         const double *theta, int64_t row_begin, int64_t row_end, double *loglik,
-                         double *grad, double *lam, double *comp, double *ell)
+                         const double *theta, double area, int64_t row_begin, int64_t row_end,
+                         double *loglik, double *grad, double *lam, double *comp, double *ell)
 {
-    if (n < 1 || !t || !x || !y || !s || !theta || !loglik)
+    if (n < 1 || !t || !x || !y || !s || !theta || !loglik || !(area >= 0.0) || !isfinite(area))
         return -1;
     if (row_begin < 0 || row_end > n || row_begin > row_end)
         return -1;
@@ -178,7 +190,7 @@ int hawkes_oracle_loglik(int64_t n, const double *t, const double *x, const doub
     for (int64_t r = 0; r < rows; ++r) {
         const int64_t i = row_begin + r;
         double rate[7], cmp[7];
-        oracle_rate(i, n, t, x, y, s, theta, rate);
+        oracle_rate(i, n, t, x, y, s, theta, area, rate);
         oracle_compensator(t[i], tN, theta, cmp);
         const double lam_i = rate[0];
         const int floored = lam_i < ORACLE_LAMBDA_FLOOR;
@@ -213,7 +225,7 @@ int hawkes_oracle_loglik(int64_t n, const double *t, const double *x, const doub
  * pin each part against an independent computation.
  */
 int hawkes_oracle_rate_parts(int64_t n, const double *t, const double *x, const double *y,
-                             const double *s, const double *theta, int64_t row_begin,
+                             const double *s, const double *theta, double area, int64_t row_begin,
                              int64_t row_end, double *bg, double *tr)
 {
     if (n < 1 || row_begin < 0 || row_end > n || row_begin > row_end || !bg || !tr)
@@ -221,7 +233,7 @@ int hawkes_oracle_rate_parts(int64_t n, const double *t, const double *x, const 
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t r = 0; r < row_end - row_begin; ++r) {
         double rate[7];
-        oracle_rate(row_begin + r, n, t, x, y, s, theta, rate);
+        oracle_rate(row_begin + r, n, t, x, y, s, theta, area, rate);
         bg[r] = rate[1 + P_MU];
         tr[r] = rate[1 + P_XI];
     }

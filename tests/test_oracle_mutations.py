@@ -38,6 +38,10 @@ MUTATIONS = [
     ("Philox round multiplier", r"0xD2E7470EE14C6C93ULL", "0xD2E7470EE14C6C95ULL"),
     ("x and y from the same uniform", r"const double uy = \(double\)\(w\[1\] >> 11\)",
      "const double uy = (double)(w[0] >> 11)"),
+    ("uniform background without 1/A", r"const double beta = n1_density\(dt, taut \* taut\) / area;",
+     "const double beta = n1_density(dt, taut * taut);"),
+    ("uniform background keeps the spatial Gaussian", r"const double beta = n1_density\(dt, taut \* taut\) / area;",
+     "const double beta = n2_density(d2, taux * taux) * n1_density(dt, taut * taut) / area;"),
 ]
 
 PIN_TESTS = [name for name in dir(pins) if name.startswith("test_")]

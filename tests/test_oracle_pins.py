@@ -374,3 +374,87 @@ def test_resample_uniform_inside_counties():
     # deterministic in (seed, iteration, n)
     x3, _ = oracle.resample(ev.county, ev.rect, seed=2000, iteration=3)
     assert np.array_equal(x, x3)
+
+
+# ------------------------------------------- the paper's uniform background
+
+AREA = 1.0e6  # km^2: a 1000 x 1000 km domain
+
+
+def test_uniform_background_two_event_closed_form():
+    """The paper's own background mu0 / A(X) times the temporal Gaussian (equation "fixed"), N = 2:
+    library densities, the source bandwidth of model 2 and the unchanged compensator."""
+    mu, tau_x, tau_t, xi, h0, omega = th = _theta(0.7, 3.0, 2.0, 0.4, 1.5, 0.3)
+    t = np.array([1.0, 2.2])
+    x = np.array([0.5, 1.7])
+    y = np.array([-0.3, 0.9])
+    s = np.array([0.6, 2.5])
+    dt = t[1] - t[0]
+    kb = stats.norm.pdf(dt, scale=tau_t) / AREA
+    kt = stats.multivariate_normal.pdf([x[1], y[1]], mean=[x[0], y[0]], cov=(h0 * s[0]) ** 2 * np.eye(2)) * \
+        stats.expon.pdf(dt, scale=1 / omega)
+    lam1, lam2 = mu * kb, mu * kb + xi * kt
+    phi = stats.norm.cdf
+    comp = sum(mu * (phi((t[1] - tm) / tau_t) - phi(-tm / tau_t)) + xi * (1 - math.exp(-omega * (t[1] - tm)))
+               for tm in t)
+    ll, g, lam, Lam, _ = oracle.loglik(t, x, y, s, th, per_row=True, area=AREA)
+    assert lam[0] == pytest.approx(lam1, rel=1e-13)
+    assert lam[1] == pytest.approx(lam2, rel=1e-13)
+    assert Lam.sum() == pytest.approx(comp, rel=1e-13)
+    assert ll == pytest.approx(math.log(lam1) + math.log(lam2) - comp, rel=1e-13)
+    assert g[1] == 0.0  # tau_x plays no part
+
+
+def test_uniform_background_sum_is_a_temporal_kde():
+    t, x, y, s = _small_events(40, 5)
+    th = _theta(0.9, 6.0, 4.0, 0.5, 3.0, 0.4)
+    bg, _ = oracle.rate_parts(t, x, y, s, th, area=AREA)
+    for n in range(len(t)):
+        other = t[t != t[n]]
+        assert bg[n] == pytest.approx(stats.norm.pdf(t[n] - other, scale=th[2]).sum() / AREA, rel=1e-12)
+
+
+def test_uniform_background_gradient_against_richardson_finite_differences():
+    ev = synth.generate(0, n=300, seed=17)
+    th = synth.theta_default()
+    _, g = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th, area=AREA)
+
+    def f(v):
+        return oracle.loglik(ev.t, ev.x, ev.y, ev.s, v, area=AREA)[0]
+
+    for k in range(6):
+        h = 1e-4 * th[k]
+        e = np.zeros(6)
+
+        def d(hh):
+            e[:] = 0.0
+            e[k] = hh
+            return (f(th + e) - f(th - e)) / (2 * hh)
+
+        rich = (4 * d(h / 2) - d(h)) / 3
+        assert g[k] == pytest.approx(rich, rel=2e-7, abs=1e-7 * abs(g).max())
+
+
+def test_uniform_background_scaling_identities():
+    """Space: l(c x, c h0; area c^2 A) = l - 2 N log c.  Time: l(c t, c tau_t, omega / c) = l - N log c.
+    Euler: mu dl/dmu + xi dl/dxi = N - Lambda."""
+    ev = synth.generate(0, n=400, seed=19)
+    th = synth.theta_default()
+    ll, g, lam, Lam, _ = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th, per_row=True, area=AREA)
+    assert (lam > 1e-40).all()
+    n = len(ev.t)
+    assert th[0] * g[0] + th[3] * g[3] == pytest.approx(n - Lam.sum(), rel=1e-12)
+    for c in (0.37, 3.0):
+        th2 = th.copy()
+        th2[4] *= c
+        ll2, _ = oracle.loglik(ev.t, c * ev.x, c * ev.y, ev.s, th2, area=c * c * AREA)
+        assert ll2 == pytest.approx(ll - 2 * n * math.log(c), rel=1e-12)
+        th3 = th.copy()
+        th3[2] *= c
+        th3[5] /= c
+        ll3, _ = oracle.loglik(c * ev.t, ev.x, ev.y, ev.s, th3, area=AREA)
+        assert ll3 == pytest.approx(ll - n * math.log(c), rel=1e-12)
+    # tau_x plays no part
+    th4 = th.copy()
+    th4[1] *= 5.0
+    assert oracle.loglik(ev.t, ev.x, ev.y, ev.s, th4, area=AREA)[0] == ll
