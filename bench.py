@@ -231,6 +231,18 @@ def main():
         log(f"fp64 evaluation: {d64 * 1e3:.1f} ms")
         del ws64
 
+    # the forward-only sweep (log-likelihood without gradient: the exact evaluations of the delayed-acceptance
+    # correction); reported apart from the loglik+grad metric
+    hk.loglik(dev, th, precision="fp32", ws=ws, out=out_ll)
+    hk.set_timing(True)
+    hk.loglik(dev, th, precision="fp32", ws=ws, out=out_ll)
+    kms_fwd = hk.last_pair_kernel_ms()
+    hk.set_timing(False)
+    torch.cuda.synchronize()
+    result["fp32_loglik_only"] = {"kernel_ms": kms_fwd, "pairs_per_s": pairs / (kms_fwd / 1e3),
+                                  "note": "forward-only sweep (S0, G0 per target), pair kernel time"}
+    log(f"fp32 loglik-only pair kernel: {kms_fwd:.1f} ms")
+
     if not args.no_skip:
         # the FP32 sweep without the background terms that are exactly zero in FP32 (time gap
         # past ~14.9 tau_t): same result, less work; reported apart from the O(N^2) metric

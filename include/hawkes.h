@@ -8,6 +8,7 @@
  *
  *   lambda_n = mu * sum_{m: t_m != t_n} N2(|x_n - x_m|^2; tau_x^2) N1(t_n - t_m; tau_t^2)
  *            + xi * sum_{m: t_m <  t_n} N2(|x_n - x_m|^2; h_m^2) omega exp(-omega (t_n - t_m)),
+ *              (with a domain area A > 0 in hawkes_events, N2(.; tau_x^2) becomes 1/A),
  *   h_m      = h0 * s_m      (per-source spatial sd; equation "varying" uses
  *                             s_m = D_m^(-1/2) for the county population density D_m),
  *   Lambda_n = mu [Phi((t_N - t_n)/tau_t) - Phi(-t_n/tau_t)] + xi [1 - exp(-omega (t_N - t_n))]
@@ -55,13 +56,20 @@ typedef struct hawkes_theta {
 
 /* One event set: n events, all arrays device-resident, length n, FP64.
  * t must be nondecreasing (t_N = t[n-1]); s is the per-event bandwidth scale
- * (> 0): 1 for the paper's model 1, D_n^(-1/2) for its model 2. */
+ * (> 0): 1 for the paper's model 1, D_n^(-1/2) for its model 2.
+ * area selects the background's spatial factor:
+ *   0      the isotropic Gaussian N2(|x_n - x_m|^2; tau_x^2) of the formula above;
+ *   > 0    the spatially uniform density 1/area (km^2) of the paper's own models
+ *          (equation "fixed": mu0 / A(X) times the temporal Gaussian); tau_x then
+ *          plays no part and its gradient component is 0.
+ * Negative or non-finite area: HAWKES_EINVAL. */
 typedef struct hawkes_events {
     int64_t n;
     const double *t;
     const double *x;
     const double *y;
     const double *s;
+    double area;
 } hawkes_events;
 
 /* Arithmetic of the O(N^2) pair sweep.  FP64: every pair term in FP64.

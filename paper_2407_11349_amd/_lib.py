@@ -43,7 +43,7 @@ class Theta(ctypes.Structure):
 
 class Events(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("t", ctypes.c_void_p), ("x", ctypes.c_void_p),
-                ("y", ctypes.c_void_p), ("s", ctypes.c_void_p)]
+                ("y", ctypes.c_void_p), ("s", ctypes.c_void_p), ("area", ctypes.c_double)]
 
 
 class HawkesError(RuntimeError):

@@ -97,8 +97,14 @@ constexpr int GS = HAWKES_GS;             // FP32 terms summed before folding in
 constexpr int64_t MAX_TARGET_WGS = 65536; // upper bound used for workspace sizing
 constexpr int64_t MAX_N = int64_t(1) << 30;
 constexpr double LOG2E = 1.4426950408889634074;
+constexpr float LN2F = 0.69314718055994530942f;
 constexpr double LAMBDA_FLOOR = 1e-40;
-constexpr double PAD_COORD = 1e15;        // padding sources sit far away: their terms are exactly 0
+// Padding sources (the tail of the last tile) sit far away in space and in
+// time, so that every one of their terms is exactly 0 in both background forms
+// (the uniform background has no spatial factor to rely on).  Their squared
+// distances stay finite in FP32.
+constexpr double PAD_COORD = 1e15;
+constexpr double PAD_TIME = -1e15;
 
 // Mean relative error of v_exp_f32 on gfx950, measured over 2^30 FP32
 // arguments spread uniformly on [-30, 0] (and, to within 2e-10, on [-12, 0]
@@ -352,12 +358,12 @@ __global__ __launch_bounds__(256) void k_stage_f32(const double *__restrict__ t,
     if (i >= n) {
         xs[i] = PAD_COORD;
         ys[i] = PAD_COORD;
-        tsd[i] = 0.0;
+        tsd[i] = PAD_TIME;
         rh[i] = rl[i] = vh[i] = vl[i] = dl[i] = uh[i] = ul[i] = 0.0f;
         if (HAWKES_IGEOM) {
             // padding sources sit at least 2^29 quanta (>= 512 scaled units) from every event
             xi[i] = yi[i] = -(1 << 30);
-            ti[i] = 0;
+            ti[i] = -(1 << 30);
         }
         return;
     }
@@ -438,6 +444,28 @@ __device__ inline float geom_d(int xn, int yn, int xm, int ym)
     const float dx = float(xn - xm), dy = float(yn - ym);
     return fmaf(dy, dy, dx * dx);
 }
+// Spatially uniform background: the exponent is the scaled time gap alone,
+// A = dt'^2, so with tied times (integer days) many pairs share one value of
+// A and its FP32 rounding would not average out; A is split into a hi part
+// (the exp2 argument) and a lo part that corrects the term to first order.
+__device__ inline void geom_da_uni(double xn, double yn, double tn, double xm, double ym, double tm, float &D,
+                                   float &A, float &Alo)
+{
+    const double dx = xn - xm, dy = yn - ym, dt = tn - tm;
+    D = float(fma(dy, dy, dx * dx));
+    const double a2 = dt * dt;
+    A = float(a2);
+    Alo = float(a2 - double(A));
+}
+__device__ inline void geom_da_uni(int xn, int yn, int tn, int xm, int ym, int tm, float &D, float &A, float &Alo)
+{
+    const float dx = float(xn - xm), dy = float(yn - ym);
+    D = fmaf(dy, dy, dx * dx);
+    const double dt = double(tn - tm);
+    const double a2 = dt * dt;  // exact: |dt| < 2^31
+    A = float(a2);
+    Alo = float(a2 - double(A));
+}
 __device__ inline double geom_dt(double tn, double tm, double) { return tn - tm; }
 __device__ inline double geom_dt(int tn, int tm, double q) { return double(tn - tm) * q; }
 
@@ -468,7 +496,7 @@ typedef double coord_t;
 #else
 #define HK_PAIR_ATTR
 #endif
-template <bool GRAD>
+template <bool GRAD, bool UNI>
 __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
 {
 #if !HAWKES_SMEM
@@ -644,16 +672,22 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
                         const float rhm = srh[m], rlm = srl[m], vhm = svh[m], vlm = svl[m], dm = sd[m];
 #pragma unroll
                         for (int q = 0; q < KT; ++q) {
-                            float D, A;
-                            geom_da(xn[q], yn[q], tsn[q], xm, ym, tm, D, A);
-                            const float b = __builtin_amdgcn_exp2f(-HK_BG_ARG(A));
+                            float D, A, Alo = 0.0f;
+                            if (UNI)
+                                geom_da_uni(xn[q], yn[q], tsn[q], xm, ym, tm, D, A, Alo);
+                            else
+                                geom_da(xn[q], yn[q], tsn[q], xm, ym, tm, D, A);
+                            float b = __builtin_amdgcn_exp2f(-HK_BG_ARG(A));
+                            if (UNI)
+                                b = fmaf(-LN2F * HK_BG_ARG(Alo), b, b);
                             const float t1 = fmaf(rlm, D, rhm * D);
                             const float E = __builtin_amdgcn_exp2f(-t1);
                             const float p = fmaf(vlm, E, vhm * E);
                             f[q][0] += b;
                             f[q][3] += p;
                             if (GRAD) {
-                                f[q][1] = fmaf(b, D, f[q][1]);
+                                if (!UNI)
+                                    f[q][1] = fmaf(b, D, f[q][1]);
                                 f[q][2] = fmaf(b, A, f[q][2]);
                                 f[q][4] = fmaf(p, t1, f[q][4]);
                                 f[q][5] = fmaf(p, dm, f[q][5]);
@@ -667,12 +701,18 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
                         const coord_t xm = sx[m], ym = sy[m], tm = st[m];
 #pragma unroll
                         for (int q = 0; q < KT; ++q) {
-                            float D, A;
-                            geom_da(xn[q], yn[q], tsn[q], xm, ym, tm, D, A);
-                            const float b = __builtin_amdgcn_exp2f(-HK_BG_ARG(A));
+                            float D, A, Alo = 0.0f;
+                            if (UNI)
+                                geom_da_uni(xn[q], yn[q], tsn[q], xm, ym, tm, D, A, Alo);
+                            else
+                                geom_da(xn[q], yn[q], tsn[q], xm, ym, tm, D, A);
+                            float b = __builtin_amdgcn_exp2f(-HK_BG_ARG(A));
+                            if (UNI)
+                                b = fmaf(-LN2F * HK_BG_ARG(Alo), b, b);
                             f[q][0] += b;
                             if (GRAD) {
-                                f[q][1] = fmaf(b, D, f[q][1]);
+                                if (!UNI)
+                                    f[q][1] = fmaf(b, D, f[q][1]);
                                 f[q][2] = fmaf(b, A, f[q][2]);
                             }
                         }
@@ -727,10 +767,15 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
                     const int gm = sg[m];
 #pragma unroll
                     for (int q = 0; q < KT; ++q) {
-                        float D, A;
-                        geom_da(xn[q], yn[q], tsn[q], xm, ym, tm, D, A);
+                        float D, A, Alo = 0.0f;
+                        if (UNI)
+                            geom_da_uni(xn[q], yn[q], tsn[q], xm, ym, tm, D, A, Alo);
+                        else
+                            geom_da(xn[q], yn[q], tsn[q], xm, ym, tm, D, A);
                         const double dt = geom_dt(tsn[q], tm, qnt);
                         float b = __builtin_amdgcn_exp2f(-HK_BG_ARG(A));
+                        if (UNI)
+                            b = fmaf(-LN2F * HK_BG_ARG(Alo), b, b);
                         b = (gm != gn[q]) ? b : 0.0f;
                         const float t1 = fmaf(rlm, D, rhm * D);
                         const float arg = float(fma(a.w2, dt, double(t1)));
@@ -740,7 +785,8 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
                         f[q][0] += b;
                         f[q][3] += p;
                         if (GRAD) {
-                            f[q][1] = fmaf(b, D, f[q][1]);
+                            if (!UNI)
+                                f[q][1] = fmaf(b, D, f[q][1]);
                             f[q][2] = fmaf(b, A, f[q][2]);
                             f[q][4] = fmaf(p, t1, f[q][4]);
                             f[q][5] = fmaf(p, float(dt), f[q][5]);
@@ -846,7 +892,7 @@ __global__ __launch_bounds__(WG) void k_pair_f64(PairF64 a)
         } else {
             fx = PAD_COORD;
             fy = PAD_COORD;
-            ft = 0.0;
+            ft = PAD_TIME;
             fu = 0.0;
             fg = INT_MAX;
         }
@@ -945,6 +991,7 @@ struct Fin {
     double mu, tau_x, tau_t, xi, h0, omega, c_b, c_g;
     double ax, at, qh;             // 1/(2 tau_x^2), 1/(2 tau_t^2), 1/(2 h0^2)
     double rescue_lambda;          // FP32 rows with lambda below this are recomputed (0: never)
+    int uniform;                   // spatially uniform background: no tau_x dependence
 };
 
 __device__ inline double std_normal_cdf(double z) { return 0.5 * erfc(-z * 0.70710678118654752440); }
@@ -971,7 +1018,7 @@ __device__ void row_terms(const Fin &f, const double S[6], double ti, double tN,
         if (!floored) {
             const double il = 1.0 / lam;
             dl[0] = B * il;
-            dl[1] = f.mu * f.c_b * (S[1] / (tx * tx * tx) - 2.0 * S[0] / tx) * il;
+            dl[1] = f.uniform ? 0.0 : f.mu * f.c_b * (S[1] / (tx * tx * tx) - 2.0 * S[0] / tx) * il;
             dl[2] = f.mu * f.c_b * (S[2] / (tt * tt * tt) - S[0] / tt) * il;
             dl[3] = T * il;
             dl[4] = f.xi * f.c_g * (S[4] / (h0 * h0 * h0) - 2.0 * S[3] / h0) * il;
@@ -1173,6 +1220,10 @@ int validate(const hawkes_events *ev, const hawkes_theta *th, int precision, int
         set_error("null event array");
         return HAWKES_EINVAL;
     }
+    if (!(ev->area >= 0.0) || !std::isfinite(ev->area)) {
+        set_error("background area %g is not finite and >= 0", ev->area);
+        return HAWKES_EINVAL;
+    }
     if (!valid_precision(precision)) {
         set_error("precision %d is not HAWKES_FP64, HAWKES_FP32 or HAWKES_FP32_SKIP", precision);
         return HAWKES_EINVAL;
@@ -1247,14 +1298,18 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
 
     const Plan P = make_plan(rows, L.num_tiles);
     const double tau_x = th->tau_x, tau_t = th->tau_t, h0 = th->h0, omega = th->omega;
+    const bool uniform = ev->area > 0.0;
     double *partials = at<double>(ws, L.partials);
     const unsigned pair_blocks = unsigned(P.num_tb * P.num_chunks);
 
     if (is_fp32(precision)) {
         StageF32 sc;
-        sc.sx = std::sqrt(LOG2E / (2.0 * tau_x * tau_x));
+        // positions are scaled by the background's spatial scale, or by the triggering
+        // bandwidth h0 when the background is spatially uniform
+        const double tau_sp = uniform ? h0 : tau_x;
+        sc.sx = std::sqrt(LOG2E / (2.0 * tau_sp * tau_sp));
         sc.st = std::sqrt(LOG2E / (2.0 * tau_t * tau_t));
-        sc.rr = (tau_x / h0) * (tau_x / h0);
+        sc.rr = (tau_sp / h0) * (tau_sp / h0);
         sc.omega = omega;
         double *xs = at<double>(ws, L.xs), *ys = at<double>(ws, L.ys), *tsd = at<double>(ws, L.tsd);
         float *rh = at<float>(ws, L.rh), *rl = at<float>(ws, L.rl), *vh = at<float>(ws, L.vh);
@@ -1297,7 +1352,7 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
         a.num_tb = P.num_tb;
         a.omega = omega;
         a.inv_st = 1.0 / sc.st;
-        a.out_s1 = 1.0 / (sc.sx * sc.sx);        // D = d^2 sx^2
+        a.out_s1 = uniform ? 0.0 : 1.0 / (sc.sx * sc.sx);  // D = d^2 sx^2
         a.out_s2 = 1.0 / (sc.st * sc.st);        // dt' = dt st
         a.out_g1 = 2.0 * h0 * h0 / LOG2E;        // t1 = u d^2 log2(e) / (2 h0^2)
         a.w2 = omega * LOG2E / sc.st;
@@ -1316,10 +1371,14 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
         a.geo = reinterpret_cast<const double *>(status) + STATUS_GEO;
         if (g_timing && (rc = record_event(g_ev_start, stream)) != HAWKES_OK)
             return rc;
-        if (grad)
-            hipLaunchKernelGGL(k_pair_f32<true>, dim3(pair_blocks), dim3(WG), 0, stream, a);
+        if (grad && uniform)
+            hipLaunchKernelGGL((k_pair_f32<true, true>), dim3(pair_blocks), dim3(WG), 0, stream, a);
+        else if (grad)
+            hipLaunchKernelGGL((k_pair_f32<true, false>), dim3(pair_blocks), dim3(WG), 0, stream, a);
+        else if (uniform)
+            hipLaunchKernelGGL((k_pair_f32<false, true>), dim3(pair_blocks), dim3(WG), 0, stream, a);
         else
-            hipLaunchKernelGGL(k_pair_f32<false>, dim3(pair_blocks), dim3(WG), 0, stream, a);
+            hipLaunchKernelGGL((k_pair_f32<false, false>), dim3(pair_blocks), dim3(WG), 0, stream, a);
         if (g_timing) {
             if ((rc = record_event(g_ev_stop, stream)) != HAWKES_OK)
                 return rc;
@@ -1344,7 +1403,7 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
         a.chunk_tiles = P.chunk_tiles;
         a.num_chunks = P.num_chunks;
         a.num_tb = P.num_tb;
-        a.ax = 1.0 / (2.0 * tau_x * tau_x);
+        a.ax = uniform ? 0.0 : 1.0 / (2.0 * tau_x * tau_x);  // uniform background: no spatial factor
         a.at = 1.0 / (2.0 * tau_t * tau_t);
         a.qh = 1.0 / (2.0 * h0 * h0);
         a.omega = omega;
@@ -1387,9 +1446,11 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
     f.xi = th->xi;
     f.h0 = h0;
     f.omega = omega;
-    f.c_b = 1.0 / (std::pow(2.0 * M_PI, 1.5) * tau_x * tau_x * tau_t);
+    f.uniform = uniform ? 1 : 0;
+    f.c_b = uniform ? 1.0 / (ev->area * std::sqrt(2.0 * M_PI) * tau_t)
+                    : 1.0 / (std::pow(2.0 * M_PI, 1.5) * tau_x * tau_x * tau_t);
     f.c_g = omega / (2.0 * M_PI * h0 * h0);
-    f.ax = 1.0 / (2.0 * tau_x * tau_x);
+    f.ax = uniform ? 0.0 : 1.0 / (2.0 * tau_x * tau_x);
     f.at = 1.0 / (2.0 * tau_t * tau_t);
     f.qh = 1.0 / (2.0 * h0 * h0);
     // Each FP32 pair term below 2^-126 may be lost to underflow; n of them

@@ -21,16 +21,18 @@ def _dev_f64(a, device) -> torch.Tensor:
 
 @dataclass
 class DeviceEvents:
-    """An event set resident in HBM (FP64 SoA: t, x, y, s)."""
+    """An event set resident in HBM (FP64 SoA: t, x, y, s).  area = 0: Gaussian spatial
+    background; area > 0: the paper's spatially uniform background 1/area (km^2)."""
 
     t: torch.Tensor
     x: torch.Tensor
     y: torch.Tensor
     s: torch.Tensor
+    area: float = 0.0
 
     @classmethod
-    def from_arrays(cls, t, x, y, s, device="cuda") -> "DeviceEvents":
-        return cls(_dev_f64(t, device), _dev_f64(x, device), _dev_f64(y, device), _dev_f64(s, device))
+    def from_arrays(cls, t, x, y, s, device="cuda", area: float = 0.0) -> "DeviceEvents":
+        return cls(_dev_f64(t, device), _dev_f64(x, device), _dev_f64(y, device), _dev_f64(s, device), float(area))
 
     @property
     def n(self) -> int:
@@ -40,7 +42,8 @@ class DeviceEvents:
         for a in (self.t, self.x, self.y, self.s):
             if a.dtype != torch.float64 or not a.is_cuda or not a.is_contiguous() or a.shape[0] != self.n:
                 raise ValueError("event arrays must be contiguous float64 CUDA tensors of equal length")
-        return _lib.Events(self.n, _lib.ptr(self.t), _lib.ptr(self.x), _lib.ptr(self.y), _lib.ptr(self.s))
+        return _lib.Events(self.n, _lib.ptr(self.t), _lib.ptr(self.x), _lib.ptr(self.y), _lib.ptr(self.s),
+                           float(self.area))
 
 
 def workspace_bytes(n: int, precision="fp32") -> int:

@@ -1,9 +1,11 @@
 """Samplers over the six log-parameters: HMC, delayed-acceptance HMC with a
-surrogate, the cut-posterior driver, and bulk-ESS / split R-hat."""
+surrogate, the paper's univariate Metropolis-Hastings, the cut-posterior driver,
+and bulk-ESS / split R-hat."""
 
 from .da_hmc import DAState, DelayedAcceptanceHMC
+from .mh import UnivariateMH
 from .ess import bulk_ess, ess, mcse_mean, split_rhat
 from .hmc import HMC, DualAveraging, HMCState, leapfrog
 
 __all__ = ["DAState", "DelayedAcceptanceHMC", "bulk_ess", "ess", "mcse_mean", "split_rhat", "HMC", "DualAveraging",
-           "HMCState", "leapfrog"]
+           "HMCState", "leapfrog", "UnivariateMH"]

@@ -159,6 +159,35 @@ def run_plain_hmc(target: HawkesCutTarget, hmc: HMC, z0, n_iter: int, it0: int, 
                        {"accept": acc / n_iter})
 
 
+def run_mh(target: HawkesCutTarget, z0, inv_mass, n_iter: int, it0: int, n_adapt=200, seed=13,
+           log=None) -> ChainResult:
+    """The paper's kernel: univariate random-walk MH sweeps (6 proposals, forward-only exact
+    densities), each after a fresh latent-location draw.  Proposal scales start at 2.4 posterior
+    sd (from the HMC warm-up) and adapt over n_adapt untimed sweeps with a diminishing rate."""
+    from .mh import UnivariateMH
+
+    mh = UnivariateMH(target, scales=2.4 * np.sqrt(np.asarray(inv_mass)), rng=np.random.default_rng(seed))
+    z = np.asarray(z0, dtype=np.float64)
+    for it in range(n_adapt):
+        target.resample(it0 + it)
+        z, _ = mh.sweep(z, target.logp(z), adapt_rate=0.5 / np.sqrt(it + 1.0))
+    mh.accepts[:] = 0
+    mh.tries[:] = 0
+    n0, g0 = target.n_loglik, target.n_grad
+    _sync()
+    t0 = time.time()
+    draws = []
+    for it in range(n_iter):
+        target.resample(it0 + n_adapt + it)
+        z, _ = mh.sweep(z, target.logp(z))
+        draws.append(z.copy())
+        if log and (it + 1) % 500 == 0:
+            log(f"mh {it + 1}/{n_iter}: acceptance {np.round(mh.acceptance(), 2)}")
+    _sync()
+    return ChainResult(np.array(draws), time.time() - t0, target.n_loglik - n0, target.n_grad - g0,
+                       {"acceptance": mh.acceptance().tolist(), "scales": mh.scales.tolist()})
+
+
 def run_da_hmc(target: HawkesCutTarget, sur: Surrogate, hmc: HMC, z0, n_iter: int, it0: int, prior_var: float,
                log=None) -> ChainResult:
     def sur_post(z):
@@ -227,8 +256,9 @@ def compare(events, county, rect, *, n_burn=1000, n_iter=2000, n_leapfrog=20, se
     it0 = n_warmup + n_burn + 1
     plain = run_plain_hmc(target, hmc, st.z, n_iter, it0, log=log)
     dah = run_da_hmc(target, sur, hmc, st.z, n_iter, it0 + n_iter + 1, target.prior_var, log=log)
+    mh = run_mh(target, st.z, hmc.inv_mass, n_iter, it0 + 2 * n_iter + 2, log=log)
     out = {"burn_in_seconds": t_burn, "surrogate": held, "step_size": hmc.eps, "n_iter": n_iter}
-    for name, r in (("plain_hmc", plain), ("da_hmc", dah)):
+    for name, r in (("plain_hmc", plain), ("da_hmc", dah), ("univariate_mh", mh)):
         s = _summary(r.draws)
         ess_min = float(np.min(s["bulk_ess"]))
         out[name] = {"seconds": r.seconds, "n_loglik": r.n_loglik, "n_grad": r.n_grad, "stats": r.stats,
@@ -238,4 +268,5 @@ def compare(events, county, rect, *, n_burn=1000, n_iter=2000, n_leapfrog=20, se
     se = np.sqrt(np.array(out["plain_hmc"]["mcse"]) ** 2 + np.array(out["da_hmc"]["mcse"]) ** 2)
     out["means_agree_within_3_mcse"] = bool(np.all(np.abs(mp - md) <= 3 * se))
     out["ess_per_s_ratio"] = out["da_hmc"]["ess_per_s"] / out["plain_hmc"]["ess_per_s"]
+    out["mh_ess_per_s_ratio_to_plain_hmc"] = out["univariate_mh"]["ess_per_s"] / out["plain_hmc"]["ess_per_s"]
     return out

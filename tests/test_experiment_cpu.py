@@ -75,3 +75,23 @@ def test_burn_in_records_tuples_and_chains_agree():
     sp, sd = ex._summary(plain.draws), ex._summary(da.draws)
     se = np.sqrt(np.array(sp["mcse"]) ** 2 + np.array(sd["mcse"]) ** 2)
     assert np.all(np.abs(np.array(sp["mean"]) - np.array(sd["mean"])) < 4.5 * se + 1e-4)
+
+
+def test_univariate_mh_chain_on_the_cut_target():
+    """The paper's univariate MH under per-iteration latent draws: 7 log-densities per sweep
+    (one after the draw, six proposals), no gradients, and means that agree with plain HMC."""
+    rng = np.random.default_rng(1)
+    A = rng.normal(size=(6, 6))
+    C = (A @ A.T / 6 + 0.3 * np.eye(6)) * 0.01
+    mu = rng.normal(size=6) * 0.1
+    Q = np.linalg.inv(C)
+    tgt = FakeCutTarget(mu, Q)
+    hmc, st, _, _ = ex.burn_in(tgt, mu, 200, n_leapfrog=10, seed=2, n_warmup=200)
+    mh = ex.run_mh(tgt, st.z, hmc.inv_mass, 3000, it0=20000)
+    assert mh.n_grad == 0 and mh.n_loglik == 3000 * 7
+    acc = np.array(mh.stats["acceptance"])
+    assert np.all((acc > 0.2) & (acc < 0.7))
+    plain = ex.run_plain_hmc(tgt, hmc, st.z, 3000, it0=40000)
+    sp, sm = ex._summary(plain.draws), ex._summary(mh.draws)
+    se = np.sqrt(np.array(sp["mcse"]) ** 2 + np.array(sm["mcse"]) ** 2)
+    assert np.all(np.abs(np.array(sp["mean"]) - np.array(sm["mean"])) < 4.5 * se + 1e-4)

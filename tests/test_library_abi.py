@@ -55,8 +55,8 @@ def test_strerror_and_codes(lib):
     assert lib.hawkes_strerror(-99) == b"unknown status"
 
 
-def _ev(n, p=0x100000):
-    return _lib.Events(n, p, p, p, p)
+def _ev(n, p=0x100000, area=0.0):
+    return _lib.Events(n, p, p, p, p, area)
 
 
 def test_host_validation_paths(lib):
@@ -68,6 +68,10 @@ def test_host_validation_paths(lib):
     assert lib.hawkes_loglik(ctypes.byref(_ev(0)), ctypes.byref(th), 1, 0, 0, fake, ws_need, fake, None) == -1
     assert lib.hawkes_loglik(ctypes.byref(_ev(1000, 0)), ctypes.byref(th), 1, 0, 1, fake, ws_need, fake, None) == -1
     assert lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(th), 3, 0, 10, fake, ws_need, fake, None) == -1
+    for bad_area in (-1.0, float("nan"), float("inf")):
+        eva = _ev(1000, area=bad_area)
+        assert lib.hawkes_loglik(ctypes.byref(eva), ctypes.byref(th), 1, 0, 10, fake, ws_need, fake, None) == -1
+        assert b"area" in lib.hawkes_last_error()
     for k in range(6):
         for bad in (0.0, -1.0, float("nan"), float("inf")):
             vals = [0.5, 10.0, 7.0, 0.3, 2.0, 0.2]

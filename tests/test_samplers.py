@@ -127,3 +127,26 @@ def test_good_surrogate_needs_few_exact_evaluations():
         st, _, _ = da.step(st)
     assert da.stats["stage2_accept"] == da.stats["stage1_accept"]
     assert tgt.calls == da.stats["stage1_accept"] <= 500
+
+
+def test_univariate_mh_recovers_gaussian_moments_and_adapts():
+    """The paper's sampler: one-coordinate random-walk updates reach the Gaussian's moments, and
+    warm-up adaptation brings every coordinate's acceptance near 0.44."""
+    from paper_2407_11349_amd.mcmc.mh import UnivariateMH
+
+    tgt, mu, C = _target(2)
+    mh = UnivariateMH(tgt, scales=np.full(6, 0.05), rng=np.random.default_rng(4))
+    z = np.zeros(6)
+    lp = tgt.logp(z)
+    for it in range(3000):
+        z, lp = mh.sweep(z, lp, adapt_rate=0.5 / np.sqrt(it + 1.0))
+    mh.accepts[:] = 0
+    mh.tries[:] = 0
+    draws = []
+    for it in range(20000):
+        z, lp = mh.sweep(z, lp)
+        draws.append(z.copy())
+    draws = np.array(draws)
+    assert np.all(np.abs(mh.acceptance() - 0.44) < 0.1)
+    _check_moments(draws, mu, C)
+    assert lp == pytest.approx(tgt.logp(z))
