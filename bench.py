@@ -138,7 +138,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the pair sweep of one GPU is the measured unit; "
-              "a multi-GPU row split is described in DESIGN.md but not run here.", file=sys.stderr)
+              "splitting target rows across GPUs is a design that this program does not run.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -159,7 +159,7 @@ def main():
         run_ess(args, hk, synth, torch)
         return
 
-    cfg = synth.CONFIGS[2]
+    cfg = synth.N1M
     ev = synth.generate(cfg, n=args.n)
     th = synth.theta_default()
     n = ev.n

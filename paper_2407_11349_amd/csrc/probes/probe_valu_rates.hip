@@ -41,6 +41,11 @@ __global__ __launch_bounds__(256) void kern(float* out, int iters, float seed)
             if (K == 9) { f[k] = f[k] * a; d[k] = d[k] + (double)f[k]; } // v_mul_f32 + v_cvt_f64_f32 + v_add_f64
             if (K == 10) { f[k] = f[k] + (float)d[k]; d[k] = d[k] * 0.99999; } // v_cvt_f32_f64 + add f32 + mul f64
             if (K == 11) f[k] = f[k] * a;                              // v_mul_f32
+            // pairs of independent chains: do two kinds share issue slots or run side by side?
+            if (K == 12) { f[k] = fmaf(f[k], a, bconst); d[k] = fma(d[k], 0.9999, 1e-7); }   // fma_f32 + fma_f64
+            if (K == 13) { f[k] = fmaf(f[k], a, bconst); iv[k] = __float_as_int(__builtin_amdgcn_exp2f(-__int_as_float(iv[k]))); } // fma_f32 + exp
+            if (K == 14) { d[k] = fma(d[k], 0.9999, 1e-7); iv[k] = __float_as_int(__builtin_amdgcn_exp2f(-__int_as_float(iv[k]))); } // fma_f64 + exp
+            if (K == 15) f[k] = float(d[k] * 0.99999 + (double)f[k]) * a;  // cvt_f64_f32 + add_f64 + cvt_f32_f64 + mul_f32
         }
     }
     float s = 0;
@@ -57,9 +62,10 @@ int main()
     CHECK(hipEventCreate(&e0));
     CHECK(hipEventCreate(&e1));
     const char* names[] = {"v_fma_f32 (literal)", "v_add_f32 (literal)", "v_fma_f64", "v_add_f64", "v_mul_f64", "v_exp_f32",
-                           "v_fma_f32 (regs)", "v_sub_u32", "add_u32+cvt_i32+add", "mul+cvt_f64_f32+add64", "cvt_f32_f64+add+mul64", "v_mul_f32"};
-    const int nops[] = {1, 1, 1, 1, 1, 1, 1, 1, 3, 3, 3, 1};
-    for (int k = 0; k < 12; ++k) {
+                           "v_fma_f32 (regs)", "v_sub_u32", "add_u32+cvt_i32+add", "mul+cvt_f64_f32+add64", "cvt_f32_f64+add+mul64", "v_mul_f32",
+                           "fma_f32 | fma_f64", "fma_f32 | exp_f32", "fma_f64 | exp_f32", "cvt64+add64+cvt32+mul32"};
+    const int nops[] = {1, 1, 1, 1, 1, 1, 1, 1, 3, 3, 3, 1, 2, 2, 2, 4};
+    for (int k = 0; k < 16; ++k) {
         float best = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
             CHECK(hipEventRecord(e0));
@@ -76,6 +82,10 @@ int main()
             case 9: hipLaunchKernelGGL(kern<9>, dim3(nb), dim3(nt), 0, 0, out, iters, 1.0f); break;
             case 10: hipLaunchKernelGGL(kern<10>, dim3(nb), dim3(nt), 0, 0, out, iters, 1.0f); break;
             case 11: hipLaunchKernelGGL(kern<11>, dim3(nb), dim3(nt), 0, 0, out, iters, 1.0f); break;
+            case 12: hipLaunchKernelGGL(kern<12>, dim3(nb), dim3(nt), 0, 0, out, iters, 1.0f); break;
+            case 13: hipLaunchKernelGGL(kern<13>, dim3(nb), dim3(nt), 0, 0, out, iters, 1.0f); break;
+            case 14: hipLaunchKernelGGL(kern<14>, dim3(nb), dim3(nt), 0, 0, out, iters, 1.0f); break;
+            case 15: hipLaunchKernelGGL(kern<15>, dim3(nb), dim3(nt), 0, 0, out, iters, 1.0f); break;
             }
             CHECK(hipGetLastError());
             CHECK(hipEventRecord(e1));

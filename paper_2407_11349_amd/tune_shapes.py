@@ -90,7 +90,7 @@ def time_shapes(names, n: int) -> None:
     from . import _lib
     from . import likelihood as hk
 
-    ev = synth.generate(2, n=n)
+    ev = synth.generate(synth.N1M, n=n)
     th = synth.theta_default()
     dev = hk.DeviceEvents.from_arrays(ev.t, ev.x, ev.y, ev.s)
     ref = None

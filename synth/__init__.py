@@ -6,6 +6,7 @@ CPU oracle and the GPU path can both read its output without sharing any of the
 method's code.
 """
 
-from .events import EventSet, CONFIGS, WorkloadConfig, generate, generate_clustered, theta_default
+from .events import N1M, N2K, N100K, WORKLOADS, EventSet, WorkloadConfig, generate, generate_clustered, theta_default
 
-__all__ = ["EventSet", "CONFIGS", "WorkloadConfig", "generate", "generate_clustered", "theta_default"]
+__all__ = ["N1M", "N2K", "N100K", "WORKLOADS", "EventSet", "WorkloadConfig", "generate", "generate_clustered",
+           "theta_default"]

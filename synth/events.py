@@ -46,15 +46,12 @@ class WorkloadConfig:
     rho_meanlog: float = 5.0
 
 
-# The five workloads: 0 = small FP64 parity case, 1 = 1e5 events, 2 = 1e6 events
-# with per-iteration location resampling, 3 and 4 reuse the data of 1 and 2.
-CONFIGS = {
-    0: WorkloadConfig("n2000_100d_200c", 2_000, 100.0, 10, 20, 1.0, 1000),
-    1: WorkloadConfig("n100k_1000d_3000c", 100_000, 1000.0, 50, 60, 1.0, 1001),
-    2: WorkloadConfig("n1m_1200d_3000c", 1_000_000, 1200.0, 50, 60, 1.5, 1002),
-}
-CONFIGS[3] = CONFIGS[1]
-CONFIGS[4] = CONFIGS[2]
+# The workloads: a small FP64 parity case, 1e5 events, and 1e6 events (the
+# likelihood benchmark, with per-iteration location resampling).
+N2K = WorkloadConfig("n2000_100d_200c", 2_000, 100.0, 10, 20, 1.0, 1000)
+N100K = WorkloadConfig("n100k_1000d_3000c", 100_000, 1000.0, 50, 60, 1.0, 1001)
+N1M = WorkloadConfig("n1m_1200d_3000c", 1_000_000, 1200.0, 50, 60, 1.5, 1002)
+WORKLOADS = {w.name: w for w in (N2K, N100K, N1M)}
 
 # Parameter vector (mu, tau_x [km], tau_t [d], xi, h0 [km], omega [1/d]).
 THETA_NAMES = ("mu", "tau_x", "tau_t", "xi", "h0", "omega")
@@ -88,13 +85,13 @@ def _county_rects(cfg: WorkloadConfig) -> np.ndarray:
     return np.stack([ix * wx, iy * wy, (ix + 1) * wx, (iy + 1) * wy], axis=1).astype(np.float64)
 
 
-def generate(k: int | WorkloadConfig, n: int | None = None, seed: int | None = None) -> EventSet:
-    """Draw workload ``k`` (an index into CONFIGS or a WorkloadConfig).
+def generate(k: str | WorkloadConfig, n: int | None = None, seed: int | None = None) -> EventSet:
+    """Draw workload ``k`` (a name in WORKLOADS or a WorkloadConfig).
 
     ``n`` and ``seed`` override the event count and seed while keeping the rest
     of the recipe (used for smaller parity cases of the same shape).
     """
-    cfg = CONFIGS[k] if isinstance(k, int) else k
+    cfg = WORKLOADS[k] if isinstance(k, str) else k
     n = cfg.n if n is None else int(n)
     seed = cfg.seed if seed is None else int(seed)
     rng = np.random.default_rng(seed)

@@ -22,10 +22,10 @@ import synth  # noqa: E402
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_values.json")
 
 CASES = {
-    # workload 1: 1e5 events over 1000 days, 3000 counties, mixture locations
-    "n100k": dict(config=1),
-    # workload 2: 1e6 events over 1200 days, 3000 counties, mixture locations
-    "n1m": dict(config=2),
+    # 1e5 events over 1000 days, 3000 counties, mixture locations
+    "n100k": synth.N100K,
+    # 1e6 events over 1200 days, 3000 counties, mixture locations
+    "n1m": synth.N1M,
 }
 
 
@@ -33,7 +33,7 @@ def main(names):
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     th = synth.theta_default()
     for name in names:
-        cfg = synth.CONFIGS[CASES[name]["config"]]
+        cfg = CASES[name]
         ev = synth.generate(cfg)
         t0 = time.time()
         ll, g = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th)

@@ -49,8 +49,8 @@ def _check(ll, g, ll_ref, g_ref, prec, what):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_config0_loglik_and_grad(prec):
-    ev = synth.generate(0)
+def test_n2000_loglik_and_grad(prec):
+    ev = synth.generate(synth.N2K)
     th = synth.theta_default()
     ll_ref, g_ref = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th)
     ll, g = _gpu_ll_grad(_dev(ev), th, prec)
@@ -64,7 +64,7 @@ def test_config0_loglik_and_grad(prec):
 @pytest.mark.parametrize("n", [1, 2, 3, 255, 256, 257, 1023, 1025, 2049, 5003])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_ragged_sizes_per_event(n, prec):
-    ev = synth.generate(0, n=n, seed=500 + n)
+    ev = synth.generate(synth.N2K, n=n, seed=500 + n)
     th = synth.theta_default()
     ll_ref, g_ref, lam_ref, comp_ref, _ = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th, per_row=True)
     dev = _dev(ev)
@@ -88,7 +88,7 @@ def test_ragged_sizes_per_event(n, prec):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_time_ties(prec):
     """Integer-day times: many exact ties, excluded from both sums."""
-    ev = synth.generate(0, n=3000, seed=42)
+    ev = synth.generate(synth.N2K, n=3000, seed=42)
     t = np.floor(ev.t)
     th = synth.theta_default()
     ll_ref, g_ref, lam_ref, _, _ = oracle.loglik(t, ev.x, ev.y, ev.s, th, per_row=True)
@@ -104,7 +104,7 @@ def test_time_ties(prec):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_row_ranges_add_up(prec):
     """Row slices (the paper's per-GPU shares) sum to the full value; empty slices give 0."""
-    ev = synth.generate(0, n=4100, seed=9)
+    ev = synth.generate(synth.N2K, n=4100, seed=9)
     th = synth.theta_default()
     dev = _dev(ev)
     ll, g = _gpu_ll_grad(dev, th, prec)
@@ -130,21 +130,21 @@ def _golden(name):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_config1_full_against_stored_oracle(prec):
+def test_n100k_full_against_stored_oracle(prec):
     gold = _golden("n100k")
     assert gold is not None, "tests/golden/oracle_values.json lacks n100k"
-    ev = synth.generate(1)
+    ev = synth.generate(synth.N100K)
     assert ev.n == gold["n"]
     th = np.array(gold["theta"])
     ll, g = _gpu_ll_grad(_dev(ev), th, prec)
     _check(ll, g, gold["loglik"], np.array(gold["grad"]), prec, "n100k")
 
 
-def test_config1_sampled_rows_precision_audit():
+def test_n100k_sampled_rows_precision_audit():
     """Per-event rates of 2000 random rows of the 1e5 workload (FP32) against the oracle;
     reports the mean and rms relative error of lambda_n (the bias that the 1e-9 target
     on the full log-likelihood depends on)."""
-    ev = synth.generate(1)
+    ev = synth.generate(synth.N100K)
     th = synth.theta_default()
     dev = _dev(ev)
     rng = np.random.default_rng(3)
@@ -160,10 +160,10 @@ def test_config1_sampled_rows_precision_audit():
     assert np.abs(rel).max() <= TOL["fp32"][2]
 
 
-def test_config2_sampled_rows_and_stability():
+def test_n1m_sampled_rows_and_stored_oracle():
     """1e6 events, 1200 days: per-event rates of sampled rows against the oracle,
     a finite log-likelihood, and (when stored) the full value against the oracle."""
-    ev = synth.generate(2)
+    ev = synth.generate(synth.N1M)
     th = synth.theta_default()
     dev = _dev(ev)
     ll, g = _gpu_ll_grad(dev, th, "fp32")
@@ -181,7 +181,7 @@ def test_config2_sampled_rows_and_stability():
 
 
 def test_resample_bitwise_equals_oracle():
-    ev = synth.generate(1)
+    ev = synth.generate(synth.N100K)
     county = torch.from_numpy(ev.county).cuda()
     rect = torch.from_numpy(ev.rect).cuda()
     x = torch.empty(ev.n, dtype=torch.float64, device="cuda")
@@ -199,7 +199,7 @@ def test_resample_bitwise_equals_oracle():
 
 
 def test_autograd_function_backward():
-    ev = synth.generate(0, n=1500, seed=5)
+    ev = synth.generate(synth.N2K, n=1500, seed=5)
     th = torch.tensor(synth.theta_default(), dtype=torch.float64, requires_grad=True)
     dev = _dev(ev)
     ll = hk.hawkes_loglik(th, dev, "fp32")
@@ -214,7 +214,7 @@ def test_autograd_function_backward():
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_bitwise_determinism(prec):
-    ev = synth.generate(0, n=7000, seed=8)
+    ev = synth.generate(synth.N2K, n=7000, seed=8)
     th = synth.theta_default()
     dev = _dev(ev)
     a = _gpu_ll_grad(dev, th, prec)
@@ -223,7 +223,7 @@ def test_bitwise_determinism(prec):
 
 
 def test_chunking_does_not_change_results_beyond_rounding():
-    ev = synth.generate(0, n=9000, seed=10)
+    ev = synth.generate(synth.N2K, n=9000, seed=10)
     th = synth.theta_default()
     dev = _dev(ev)
     lib = _lib.load()
@@ -240,7 +240,7 @@ def test_chunking_does_not_change_results_beyond_rounding():
 
 
 def test_device_data_checks():
-    ev = synth.generate(0, n=600, seed=2)
+    ev = synth.generate(synth.N2K, n=600, seed=2)
     th = synth.theta_default()
     t = ev.t.copy()
     t[100], t[101] = t[101], t[100]
@@ -262,7 +262,7 @@ def test_device_data_checks():
 
 
 def test_pair_kernel_timing_hook():
-    ev = synth.generate(0, n=20000, seed=1)
+    ev = synth.generate(synth.N2K, n=20000, seed=1)
     dev = _dev(ev)
     hk.set_timing(True)
     try:
@@ -298,7 +298,7 @@ def test_fp32_rescue_of_underflow_limited_rows():
 def test_fp32_model1_shared_bandwidth(h0):
     """The paper's model 1: every source has the same spatial sd (s = 1), so a rounding of
     the per-source exponent scale would be shared by all triggering terms."""
-    ev = synth.generate(1, n=20000, seed=71)
+    ev = synth.generate(synth.N100K, n=20000, seed=71)
     s = np.ones(ev.n)
     th = synth.theta_default()
     th[4] = h0

@@ -39,7 +39,7 @@ def _dev(ev, t=None):
 
 def test_skip_is_bitwise_fp32_when_chunks_are_single_tiles():
     # 2e4 events over 1000 days: 79 tiles, 20 target blocks, so every chunk is one tile
-    ev = synth.generate(1, n=20000, seed=31)
+    ev = synth.generate(synth.N100K, n=20000, seed=31)
     th = synth.theta_default()
     dev = _dev(ev)
     full = _run(dev, th, "fp32")
@@ -53,9 +53,9 @@ def test_skip_is_bitwise_fp32_when_chunks_are_single_tiles():
     np.testing.assert_allclose(skip[1], g_ref, rtol=TOL_G)
 
 
-def test_skip_config1_against_stored_oracle_and_fp32():
+def test_skip_n100k_against_stored_oracle_and_fp32():
     gold = json.load(open(GOLDEN))["n100k"]
-    ev = synth.generate(1)
+    ev = synth.generate(synth.N100K)
     th = np.array(gold["theta"])
     dev = _dev(ev)
     ll_s, g_s = hk.loglik_grad(dev, th, precision="fp32_skip")
@@ -72,7 +72,7 @@ def test_skip_config1_against_stored_oracle_and_fp32():
 
 @pytest.mark.parametrize("n", [1, 2, 3, 257, 1025, 5003])
 def test_skip_ragged_sizes_per_event(n):
-    ev = synth.generate(0, n=n, seed=900 + n)
+    ev = synth.generate(synth.N2K, n=n, seed=900 + n)
     th = synth.theta_default()
     th[2] = 0.5  # tau_t = 0.5 d over 100 days: most of the span is past the gap
     _, _, lam_ref, comp_ref, _ = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th, per_row=True)
@@ -88,7 +88,7 @@ def test_skip_ragged_sizes_per_event(n):
 def test_skip_short_tau_t_and_ties():
     """Integer-day times (ties) and tau_t = 0.3 d: almost every earlier tile is swept for
     the triggering terms only, almost every later one is not visited."""
-    ev = synth.generate(0, n=6000, seed=12)
+    ev = synth.generate(synth.N2K, n=6000, seed=12)
     t = np.floor(ev.t)
     th = synth.theta_default()
     th[2] = 0.3
@@ -102,7 +102,7 @@ def test_skip_short_tau_t_and_ties():
 
 
 def test_skip_row_ranges_add_up():
-    ev = synth.generate(1, n=30000, seed=5)
+    ev = synth.generate(synth.N100K, n=30000, seed=5)
     th = synth.theta_default()
     dev = _dev(ev)
     ll, g, _, _ = _run(dev, th, "fp32_skip")

@@ -40,7 +40,7 @@ def _check(ll, g, ll_ref, g_ref, prec, what):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_skip"])
 def test_uniform_background_n2000(prec):
-    ev = synth.generate(0)
+    ev = synth.generate(synth.N2K)
     th = synth.theta_default()
     ll_ref, g_ref, lam_ref, _, _ = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th, per_row=True, area=AREA)
     dev = hk.DeviceEvents.from_arrays(ev.t, ev.x, ev.y, ev.s, area=AREA)
@@ -53,7 +53,7 @@ def test_uniform_background_n2000(prec):
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_uniform_background_n20000_model1_and_model2(prec):
     """1000 days, 3000 counties: the paper's model 2 (density-scaled bandwidths) and model 1 (s = 1)."""
-    ev = synth.generate(1, n=20000, seed=23)
+    ev = synth.generate(synth.N100K, n=20000, seed=23)
     th = synth.theta_default()
     for s, name in ((ev.s, "model2"), (np.ones(ev.n), "model1")):
         ll_ref, g_ref = oracle.loglik(ev.t, ev.x, ev.y, s, th, area=AREA)
@@ -66,7 +66,7 @@ def test_uniform_background_n20000_model1_and_model2(prec):
 def test_uniform_background_integer_day_ties(prec):
     """Integer-day times: the background depends on the time gap alone, so every pair with the same
     gap shares one exponent; the hi/lo split of that exponent keeps the FP32 sum unbiased."""
-    ev = synth.generate(1, n=20000, seed=29)
+    ev = synth.generate(synth.N100K, n=20000, seed=29)
     t = np.floor(ev.t)
     th = synth.theta_default()
     ll_ref, g_ref, lam_ref, _, _ = oracle.loglik(t, ev.x, ev.y, ev.s, th, per_row=True, area=AREA)
@@ -79,7 +79,7 @@ def test_uniform_background_integer_day_ties(prec):
 
 
 def test_uniform_background_rows_of_n100k_and_additivity():
-    ev = synth.generate(1)
+    ev = synth.generate(synth.N100K)
     th = synth.theta_default()
     dev = hk.DeviceEvents.from_arrays(ev.t, ev.x, ev.y, ev.s, area=AREA)
     ll, g = _run(dev, th, "fp32")

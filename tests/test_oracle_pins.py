@@ -143,7 +143,7 @@ def test_compensator_against_numerical_integration_of_the_rate():
 # ------------------------------------------------------------------ gradient
 
 def test_gradient_against_richardson_finite_differences():
-    ev = synth.generate(0, n=300, seed=7)
+    ev = synth.generate(synth.N2K, n=300, seed=7)
     th = synth.theta_default()
     _, g = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th)
 
@@ -164,7 +164,7 @@ def test_gradient_against_richardson_finite_differences():
 
 def test_euler_identity_mu_xi():
     """lambda_n is linear in (mu, xi) and Lambda too, so mu*dl/dmu + xi*dl/dxi = N - Lambda."""
-    ev = synth.generate(0, n=500, seed=3)
+    ev = synth.generate(synth.N2K, n=500, seed=3)
     th = synth.theta_default()
     ll, g, lam, Lam, _ = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th, per_row=True)
     assert (lam > 1e-40).all()
@@ -175,7 +175,7 @@ def test_euler_identity_mu_xi():
 
 def test_space_scaling_identity():
     """l(c x, c tau_x, c h0) = l - 2 N log c: both spatial densities are 2-D."""
-    ev = synth.generate(0, n=400, seed=11)
+    ev = synth.generate(synth.N2K, n=400, seed=11)
     th = synth.theta_default()
     ll, _ = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th)
     for c in (0.37, 3.0):
@@ -188,7 +188,7 @@ def test_space_scaling_identity():
 
 def test_time_scaling_identity():
     """l(c t, c tau_t, omega / c) = l - N log c, Lambda unchanged: both time kernels are densities."""
-    ev = synth.generate(0, n=400, seed=12)
+    ev = synth.generate(synth.N2K, n=400, seed=12)
     th = synth.theta_default()
     ll, _, _, Lam, _ = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th, per_row=True)
     for c in (0.5, 4.0):
@@ -201,7 +201,7 @@ def test_time_scaling_identity():
 
 
 def test_translation_rotation_and_permutation_invariance():
-    ev = synth.generate(0, n=300, seed=13)
+    ev = synth.generate(synth.N2K, n=300, seed=13)
     th = synth.theta_default()
     ll, g = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th)
     a = 0.7
@@ -294,7 +294,7 @@ def test_floor_of_tiny_rates():
 
 
 def test_row_range_additivity():
-    ev = synth.generate(0, n=257, seed=21)
+    ev = synth.generate(synth.N2K, n=257, seed=21)
     th = synth.theta_default()
     ll, g = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th)
     cuts = [0, 1, 64, 200, 257]
@@ -360,7 +360,7 @@ def test_philox_matches_numpy_bit_generator():
 
 
 def test_resample_uniform_inside_counties():
-    ev = synth.generate(0, n=20000, seed=31)
+    ev = synth.generate(synth.N2K, n=20000, seed=31)
     x, y = oracle.resample(ev.county, ev.rect, seed=2000, iteration=3)
     r = ev.rect[ev.county]
     assert ((x >= r[:, 0]) & (x < r[:, 2]) & (y >= r[:, 1]) & (y < r[:, 3])).all()
@@ -415,7 +415,7 @@ def test_uniform_background_sum_is_a_temporal_kde():
 
 
 def test_uniform_background_gradient_against_richardson_finite_differences():
-    ev = synth.generate(0, n=300, seed=17)
+    ev = synth.generate(synth.N2K, n=300, seed=17)
     th = synth.theta_default()
     _, g = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th, area=AREA)
 
@@ -438,7 +438,7 @@ def test_uniform_background_gradient_against_richardson_finite_differences():
 def test_uniform_background_scaling_identities():
     """Space: l(c x, c h0; area c^2 A) = l - 2 N log c.  Time: l(c t, c tau_t, omega / c) = l - N log c.
     Euler: mu dl/dmu + xi dl/dxi = N - Lambda."""
-    ev = synth.generate(0, n=400, seed=19)
+    ev = synth.generate(synth.N2K, n=400, seed=19)
     th = synth.theta_default()
     ll, g, lam, Lam, _ = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th, per_row=True, area=AREA)
     assert (lam > 1e-40).all()
