@@ -33,6 +33,8 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector: 256 CU x 2.4 GHz x 256 FLOP/clk
 # algorithmic FLOP per pair of the fused sweep (FMA = 2, add/sub/mul = 1; exp counted apart):
 # background 15 for every pair, triggering 10 more for causal pairs
 FLOP_BG, FLOP_TRIG = 15, 10
+# the symmetric sweep adds a pair's background term to the source's sums too: 1 add + 2 FMA
+FLOP_COL = 5
 
 
 def log(msg):
@@ -173,6 +175,10 @@ def main():
     bg_pairs, causal_pairs = pair_counts(ev.t)
     flop_per_launch = FLOP_BG * bg_pairs + FLOP_TRIG * causal_pairs
     exp_per_launch = bg_pairs + causal_pairs
+    # what the symmetric sweep executes: each background term once for the pair (about half of
+    # bg_pairs, exactly so without ties) plus its column sums (3 accumulations, FLOP_COL)
+    flop_executed = (FLOP_BG + FLOP_COL) * bg_pairs // 2 + FLOP_TRIG * causal_pairs
+    exp_executed = bg_pairs // 2 + causal_pairs
 
     def step(it):
         hk.resample_locations(county, rect, seed, it, dev.x, dev.y)
@@ -215,7 +221,13 @@ def main():
         "roofline": {"bound": "alu", "kernel": "k_pair_f32<grad>", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": measured_traffic(), "kernel_ms": kms, "kernel_source_hash": kernel_source_hash(), "flop_per_launch": flop_per_launch,
-                     "exp_per_launch": exp_per_launch, "exp_per_s": exp_per_launch / (kms / 1e3)},
+                     "exp_per_launch": exp_per_launch, "exp_per_s": exp_per_launch / (kms / 1e3),
+                     "executed": {"flop_per_launch": flop_executed, "exp_per_launch": exp_executed,
+                                  "achieved": flop_executed / (kms / 1e3) / 1e12,
+                                  "frac": flop_executed / (kms / 1e3) / 1e12 / PEAK_FP32_TFLOPS,
+                                  "note": "FLOP the symmetric sweep performs (each background term "
+                                          "once per pair, plus column sums); frac above uses the "
+                                          "fixed per-ordered-pair count"}},
     }
 
     if not args.no_fp64:

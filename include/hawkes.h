@@ -74,15 +74,20 @@ typedef struct hawkes_events {
 
 /* Arithmetic of the O(N^2) pair sweep.  FP64: every pair term in FP64.
  * FP32: pair terms in FP32 (pair differences formed in FP64 and rounded once,
- * per-tile FP32 partial sums folded into FP64 accumulators); the per-event
- * log, the compensator and all reductions stay in FP64.
+ * FP32 partial sums of a few terms folded into FP64 accumulators); the
+ * per-event log, the compensator and all reductions stay in FP64.  Over the
+ * whole event set (row range [0, n)) the FP32 sweep uses the symmetry of the
+ * background term: each term b_nm = b_mn of two events in strictly ordered
+ * 512-event blocks is evaluated once and added to both events' sums.
  * FP32_SKIP: the FP32 sweep, leaving out every background term that is
  * exactly zero in FP32 because the scaled time gap alone makes its exponent
  * exceed 160 (|t_n - t_m| > sqrt(2 * 160 / log2(e)) tau_t, about 14.9 tau_t):
- * whole source tiles that late are not visited and tiles that early sweep the
- * triggering terms only.  The result equals FP32 up to the FP64 summation
- * order of the chunk partials (identical when each chunk is one tile); the
- * work falls when the time span is long against tau_t. */
+ * source tiles that early sweep the triggering terms only (and, for a row
+ * range, tiles that late are not visited).  The result equals FP32 up to the
+ * FP64 summation order of partial sums (identical over the whole set); the
+ * work falls when the time span is long against tau_t.
+ * Results are bitwise reproducible for a given event set, theta, precision,
+ * row range and tuning (below). */
 enum hawkes_precision { HAWKES_FP64 = 0, HAWKES_FP32 = 1, HAWKES_FP32_SKIP = 2 };
 
 enum hawkes_status {
@@ -96,7 +101,9 @@ enum hawkes_status {
 };
 
 /* Bytes of workspace the likelihood calls need for n events at `precision`
- * (0 if the arguments are invalid).  Grows linearly with n. */
+ * (0 if the arguments are invalid).  FP64: linear in n.  FP32: the symmetric
+ * sweep keeps 9 doubles per event for each of up to 160 event groups (about
+ * 11.5 GB at n = 10^6), so the size grows with n as n * min(n / 512, 160). */
 size_t hawkes_workspace_bytes(int64_t n, int precision);
 
 /* Log-likelihood of rows [row_begin, row_end):  *d_loglik = sum_n l_n
@@ -148,11 +155,21 @@ int hawkes_workspace_status(const void *ws, int *status, void *stream);
 int hawkes_set_timing(int enable);
 int hawkes_last_pair_kernel_ms(float *ms);
 
-/* Tuning: the number of workgroups the pair sweep aims for per call (the
- * source range is split into chunks so that target blocks x chunks is about
- * this many; 1 <= wgs <= 65536; default 32768).  Results do not depend on it
+/* Tuning: the number of workgroups the row sweep (FP64, and FP32 over a row
+ * range) aims for per call (the source range is split into chunks so that
+ * target blocks x chunks is about this many; 1 <= wgs <= 65536; default
+ * 32768).  Results do not depend on it
  * beyond FP rounding of the chunk partial sums.  Process-wide setting. */
 int hawkes_tune_target_workgroups(int64_t wgs);
+
+/* Tuning: the symmetric FP32 sweep over the whole event set splits the
+ * events into about `groups` row groups and as many column groups (one
+ * workgroup per pair of groups it needs, about groups^2 / 2);
+ * 0 <= groups <= 160, default 160; 0 makes whole-set calls take the row
+ * sweep too.  Results do not depend on it beyond FP64 summation order of the
+ * partial sums (0 changes the order of the FP32 background sums as well).
+ * Process-wide setting. */
+int hawkes_tune_symmetric_groups(int64_t groups);
 
 /* Message for a status code, and the calling thread's last error message. */
 const char *hawkes_strerror(int status);

@@ -29,7 +29,8 @@ HAWKES_EDATA = -6
 EXPORTS = (
     "hawkes_workspace_bytes", "hawkes_loglik", "hawkes_loglik_grad", "hawkes_event_terms",
     "hawkes_resample_locations", "hawkes_workspace_status", "hawkes_set_timing",
-    "hawkes_last_pair_kernel_ms", "hawkes_tune_target_workgroups", "hawkes_strerror", "hawkes_last_error",
+    "hawkes_last_pair_kernel_ms", "hawkes_tune_target_workgroups", "hawkes_tune_symmetric_groups",
+    "hawkes_strerror", "hawkes_last_error",
     # include/hawkes_mlp.h
     "hawkes_mlp_state_bytes", "hawkes_mlp_workspace_bytes", "hawkes_mlp_load", "hawkes_mlp_store",
     "hawkes_mlp_forward", "hawkes_mlp_loss_grad", "hawkes_mlp_adam_step",
@@ -77,6 +78,7 @@ def load(path: Path | str | None = None) -> ctypes.CDLL:
     lib.hawkes_set_timing.argtypes = [ctypes.c_int]
     lib.hawkes_last_pair_kernel_ms.argtypes = [ctypes.POINTER(ctypes.c_float)]
     lib.hawkes_tune_target_workgroups.argtypes = [i64]
+    lib.hawkes_tune_symmetric_groups.argtypes = [i64]
     lib.hawkes_mlp_state_bytes.argtypes = []
     lib.hawkes_mlp_state_bytes.restype = ctypes.c_size_t
     lib.hawkes_mlp_workspace_bytes.argtypes = [i64]
@@ -93,8 +95,8 @@ def load(path: Path | str | None = None) -> ctypes.CDLL:
     lib.hawkes_last_error.restype = ctypes.c_char_p
     for name in ("hawkes_loglik", "hawkes_loglik_grad", "hawkes_event_terms", "hawkes_resample_locations",
                  "hawkes_workspace_status", "hawkes_set_timing", "hawkes_last_pair_kernel_ms",
-                 "hawkes_tune_target_workgroups", "hawkes_mlp_load", "hawkes_mlp_store", "hawkes_mlp_forward",
-                 "hawkes_mlp_loss_grad", "hawkes_mlp_adam_step"):
+                 "hawkes_tune_target_workgroups", "hawkes_tune_symmetric_groups", "hawkes_mlp_load",
+                 "hawkes_mlp_store", "hawkes_mlp_forward", "hawkes_mlp_loss_grad", "hawkes_mlp_adam_step"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -8,15 +8,16 @@
 // Pipeline of one call (all on the caller's stream, no allocation):
 //   1. k_clear_status, k_stage_common   tie-group ids, tile time ranges, data checks
 //   2. k_stage_f32 (FP32 only)          per-theta source records in SoA layout
+//      k_sym_bounds, k_sym_plan         (symmetric sweep) block order relations
 //   3. k_pair_f32 / k_pair_f64          the pair sweep: per target row, six sums
-//                                       over all sources of one source chunk
+//                                       over the sources of one source range
 //   4. k_finalize                       per row: lambda_n, log, gradient terms,
 //                                       compensator (FP64); FP32 rows whose sums
 //                                       are underflow-limited go on a rescue list
 //   5. k_rescue                         those rows again, every pair in FP64
 //   6. k_blocksum, k_reduce             fixed-order FP64 sums of the row values
 //
-// Pair sums of target n (App. A of the design notes; u_m = s_m^-2):
+// Pair sums of target n (u_m = s_m^-2):
 //   S0 = sum_{t_m != t_n} b_nm,  Sd2 = sum b d^2,  Sdt2 = sum b dt^2,
 //   G0 = sum_{t_m < t_n} u_m e_nm,  G1 = sum u_m e (u_m d^2),  G2 = sum u_m e dt,
 //   b_nm = exp(-d^2/(2 tau_x^2) - dt^2/(2 tau_t^2)),  e_nm = exp(-u_m d^2/(2 h0^2) - omega dt).
@@ -24,14 +25,19 @@
 //   lambda_n = mu c_b S0 + xi c_g G0, and every d lambda_n / d theta is a
 //   linear combination of the six sums.
 //
-// Work decomposition: a workgroup owns TB = 512 target rows (2 per lane) and
-// one chunk of source tiles; TS = 256 sources per tile are staged through LDS
-// (double buffered) and read by all lanes as broadcasts.  Each
-// (target block, tile) pair is classified from the tile's and the block's
-// time ranges: CAUSAL (every source strictly earlier than every target:
-// background + triggering, no masks), ANTI (every source strictly later:
-// background only) or MIXED (per-pair masks from tie-group ids).  Causality
-// is never decided from rounded times.
+// Work decomposition: TS = 256 sources per tile are staged through LDS
+// (double buffered) and read by all lanes as broadcasts; a target block of
+// TB = 512 rows sits in registers (2 per lane).  Each (target block, tile)
+// pair is classified from the tile's and the block's time ranges: CAUSAL
+// (every source strictly earlier than every target: background +
+// triggering, no masks), ANTI (every source strictly later: background
+// only) or MIXED (per-pair masks from tie-group ids).  Causality is never
+// decided from rounded times.  The background kernel is symmetric in the
+// pair, so over the whole event set each strictly ordered pair of blocks is
+// swept once, from the later block, and its background terms are added to
+// both blocks' rows (the FP32 symmetric sweep); a row range sweeps all its
+// tiles.  Partial sums go to per-source-range slots that the finalize adds
+// in a fixed order, so results are bitwise reproducible.
 //
 // Skip mode (HAWKES_FP32_SKIP): the same FP32 sweep without the pairs whose
 // background term is exactly zero in FP32 because the time gap alone puts its
@@ -47,7 +53,9 @@
 //    exp(-omega dt) = exp(-omega (t_n - T_k)) * exp(-omega (T_k - t_m)); the
 //    source factor is folded into v_m = u_m exp(-omega (T_k - t_m)) at
 //    staging and the target factor is applied in FP64 per tile;
-//  * each tile's 256-term FP32 partial sums are folded into FP64 accumulators.
+//  * FP32 partial sums of 8 terms are folded into FP64 accumulators; the
+//    column sums of the symmetric sweep are FP32 sums over a wave's 128
+//    targets, folded into FP64 per tile.
 
 #include <hip/hip_runtime.h>
 
@@ -73,28 +81,19 @@ namespace {
 #define HAWKES_GS 8
 #endif
 #ifndef HAWKES_UJ
-#define HAWKES_UJ HAWKES_GS
-#endif
-// Pair geometry of the FP32 sweep: 0 = FP64 differences of pre-scaled
-// coordinates; 1 = exact int32 differences of fixed-point coordinates.
-#ifndef HAWKES_IGEOM
-#define HAWKES_IGEOM 0
-#endif
-// Source records: 0 = staged through LDS (double-buffered, a barrier per
-// tile); 1 = read by every wave straight from global memory with
-// wave-uniform (scalar) loads, no LDS and no barriers.
-#ifndef HAWKES_SMEM
-#define HAWKES_SMEM 0
+#define HAWKES_UJ 2
 #endif
 #define HK_STR(x) #x
 #define HK_UNROLL(n) _Pragma(HK_STR(unroll n))
 
 constexpr int TS = 256;                   // sources per LDS tile
 constexpr int WG = 256;                   // threads per workgroup (4 wave64)
+constexpr int NW = WG / 64;               // waves per workgroup
 constexpr int KT = HAWKES_KT;             // target rows per lane
 constexpr int TB = WG * KT;               // target rows per workgroup
 constexpr int GS = HAWKES_GS;             // FP32 terms summed before folding into FP64
 constexpr int64_t MAX_TARGET_WGS = 65536; // upper bound used for workspace sizing
+constexpr int MAX_SYM_GROUPS = 160;       // row / column groups of the symmetric sweep (workspace bound)
 constexpr int64_t MAX_N = int64_t(1) << 30;
 constexpr double LOG2E = 1.4426950408889634074;
 constexpr float LN2F = 0.69314718055994530942f;
@@ -131,11 +130,32 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ------------------------------------------------------------------ layout
 
+// Groups of the symmetric sweep: about `groups` row groups of rr target
+// blocks and as many column groups of ct = KT rr source tiles (the same
+// number of events), so the workgroup count is about groups^2 / 2 and the
+// partials take 9 doubles per row and group.
+struct SymPlan {
+    int rr = 1, ct = 1, num_gr = 0, num_gc = 0;
+};
+
+SymPlan make_sym_plan(int64_t num_tb, int64_t num_tiles, int groups)
+{
+    SymPlan S;
+    const int64_t s = ceil_div(num_tb, groups);
+    S.rr = int(s);
+    S.ct = int(KT * s);
+    S.num_gr = int(ceil_div(num_tb, S.rr));
+    S.num_gc = int(ceil_div(num_tiles, S.ct));
+    return S;
+}
+
+int g_sym_groups = 160;
+
 struct Layout {
     int64_t n = 0, n_pad = 0, num_tiles = 0, part_elems = 0, max_blocks = 0, rows_cap = 0;
     size_t status = 0, g = 0, tile = 0, rowvals = 0, rescue = 0;
     size_t xs = 0, ys = 0, tsd = 0, rh = 0, rl = 0, vh = 0, vl = 0, dl = 0, uh = 0, ul = 0;
-    size_t xi = 0, yi = 0, ti = 0;
+    size_t sblk = 0, eblk = 0, gchi = 0, g0 = 0;
     size_t partials = 0, blocks = 0, total = 0;
 };
 
@@ -146,12 +166,20 @@ Layout make_layout(int64_t n, int precision)
     L.num_tiles = ceil_div(n, TS);
     L.n_pad = L.num_tiles * TS;
     const int64_t tb_max = ceil_div(n, TB);
+    L.max_blocks = ceil_div(n, WG);
+    L.rows_cap = tb_max * TB;
+    // row sweep: target blocks x chunks partial slots of 6 sums
     int64_t slots = L.num_tiles * tb_max;
     if (slots > MAX_TARGET_WGS + tb_max)
         slots = MAX_TARGET_WGS + tb_max;
     L.part_elems = slots * TB * 6;
-    L.max_blocks = ceil_div(n, WG);
-    L.rows_cap = tb_max * TB;
+    if (is_fp32(precision)) {
+        // symmetric sweep at the largest group count: 6 row and 3 column sums per group
+        const SymPlan S = make_sym_plan(tb_max, L.num_tiles, MAX_SYM_GROUPS);
+        const int64_t sym_elems = (6 * int64_t(S.num_gc) + 3 * int64_t(S.num_gr)) * L.rows_cap;
+        if (sym_elems > L.part_elems)
+            L.part_elems = sym_elems;
+    }
 
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -173,11 +201,10 @@ Layout make_layout(int64_t n, int precision)
         L.dl = take(sizeof(float) * L.n_pad);
         L.uh = take(sizeof(float) * L.n_pad);
         L.ul = take(sizeof(float) * L.n_pad);
-        if (HAWKES_IGEOM) {
-            L.xi = take(sizeof(int) * L.n_pad);
-            L.yi = take(sizeof(int) * L.n_pad);
-            L.ti = take(sizeof(int) * L.n_pad);
-        }
+        L.sblk = take(sizeof(int) * tb_max);
+        L.eblk = take(sizeof(int) * tb_max);
+        L.gchi = take(sizeof(int) * MAX_SYM_GROUPS);
+        L.g0 = take(sizeof(int) * MAX_SYM_GROUPS);
     }
     L.partials = take(sizeof(double) * L.part_elems);
     L.blocks = take(sizeof(double) * 7 * L.max_blocks);
@@ -187,7 +214,7 @@ Layout make_layout(int64_t n, int precision)
     return L;
 }
 
-// Work plan of one call: target blocks over the row range, source chunks.
+// Work plan of the row sweep: target blocks over the row range, source chunks.
 struct Plan {
     int64_t rows = 0, num_tb = 0, rows_pad = 0, chunk_tiles = 0, num_chunks = 0;
 };
@@ -213,48 +240,10 @@ Plan make_plan(int64_t rows, int64_t num_tiles)
 // ------------------------------------------------------------- kernels
 
 // status[0]: data-check flags; status[1]: number of rows on the rescue list.
-// Bytes 64..87 of the status block: maxima of |x|, |y|, |t| (FP64 bit
-// patterns, which order like the values for non-negative numbers); bytes
-// 128..143: the fixed-point quantum q and q^2 of the integer geometry.
-constexpr int STATUS_EXT = 8, STATUS_GEO = 16;  // offsets in 8-byte words
 __global__ void k_clear_status(int *status)
 {
     status[0] = 0;
     status[1] = 0;
-    unsigned long long *ext = reinterpret_cast<unsigned long long *>(status) + STATUS_EXT;
-    ext[0] = ext[1] = ext[2] = 0ull;
-}
-
-// Largest |x|, |y| and |t| of the events (one atomic per workgroup and value).
-__global__ __launch_bounds__(256) void k_extent(const double *__restrict__ t, const double *__restrict__ x,
-                                                const double *__restrict__ y, int64_t n, int *status)
-{
-    __shared__ double red[3][256];
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    double ax = 0.0, ay = 0.0, at = 0.0;
-    if (i < n) {
-        ax = fabs(x[i]);
-        ay = fabs(y[i]);
-        at = fabs(t[i]);
-        // non-finite values are flagged by the data checks; keep them out of the extents
-        ax = isfinite(ax) ? ax : 0.0;
-        ay = isfinite(ay) ? ay : 0.0;
-        at = isfinite(at) ? at : 0.0;
-    }
-    red[0][threadIdx.x] = ax;
-    red[1][threadIdx.x] = ay;
-    red[2][threadIdx.x] = at;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
-            for (int z = 0; z < 3; ++z)
-                red[z][threadIdx.x] = fmax(red[z][threadIdx.x], red[z][threadIdx.x + w]);
-        __syncthreads();
-    }
-    if (threadIdx.x < 3) {
-        unsigned long long *ext = reinterpret_cast<unsigned long long *>(status) + STATUS_EXT;
-        atomicMax(&ext[threadIdx.x], (unsigned long long)__double_as_longlong(red[threadIdx.x][0]));
-    }
 }
 
 __global__ void k_zero_outputs(double *loglik, double *grad)
@@ -330,41 +319,16 @@ __global__ __launch_bounds__(256) void k_stage_f32(const double *__restrict__ t,
                                                    float *__restrict__ rh, float *__restrict__ rl,
                                                    float *__restrict__ vh, float *__restrict__ vl,
                                                    float *__restrict__ dl, float *__restrict__ uh,
-                                                   float *__restrict__ ul, int *status, int *__restrict__ xi,
-                                                   int *__restrict__ yi, int *__restrict__ ti)
+                                                   float *__restrict__ ul)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n_pad)
         return;
-    // fixed-point quantum q = 2^-k of the scaled coordinates: every |coordinate| / q
-    // stays within 2^29, so differences fit int32; k <= 20 keeps every time
-    // difference that can give a nonzero background term (|dt'| < 16) exact in FP32
-    double q = 1.0, q2 = 1.0;
-    if (HAWKES_IGEOM) {
-        const unsigned long long *ext = reinterpret_cast<const unsigned long long *>(status) + STATUS_EXT;
-        const double mxy = fmax(__longlong_as_double((long long)ext[0]), __longlong_as_double((long long)ext[1]));
-        const double m = fmax(mxy * c.sx, __longlong_as_double((long long)ext[2]) * c.st);
-        int e = 0;
-        frexp(m, &e);  // m < 2^e
-        const int k = (29 - e < 20) ? 29 - e : 20;
-        q = ldexp(1.0, -k);
-        q2 = q * q;
-        if (i == 0) {
-            double *geo = reinterpret_cast<double *>(status) + STATUS_GEO;
-            geo[0] = q;
-            geo[1] = q2;
-        }
-    }
     if (i >= n) {
         xs[i] = PAD_COORD;
         ys[i] = PAD_COORD;
         tsd[i] = PAD_TIME;
         rh[i] = rl[i] = vh[i] = vl[i] = dl[i] = uh[i] = ul[i] = 0.0f;
-        if (HAWKES_IGEOM) {
-            // padding sources sit at least 2^29 quanta (>= 512 scaled units) from every event
-            xi[i] = yi[i] = -(1 << 30);
-            ti[i] = -(1 << 30);
-        }
         return;
     }
     const int64_t k = i / TS;
@@ -375,14 +339,8 @@ __global__ __launch_bounds__(256) void k_stage_f32(const double *__restrict__ t,
     xs[i] = x[i] * c.sx;
     ys[i] = y[i] * c.sx;
     tsd[i] = t[i] * c.st;
-    if (HAWKES_IGEOM) {
-        xi[i] = int(rint(x[i] * c.sx / q));
-        yi[i] = int(rint(y[i] * c.sx / q));
-        ti[i] = int(rint(t[i] * c.st / q));
-    }
     float hi, lo;
-    // the triggering exponent scale takes the quantum's square (a power of two: exact)
-    split_f32(u * c.rr * q2, hi, lo);
+    split_f32(u * c.rr, hi, lo);
     rh[i] = hi;
     rl[i] = lo;
     split_f32(u * exp(-c.omega * d), hi, lo);
@@ -399,28 +357,30 @@ struct PairF32 {
     const float *rh, *rl, *vh, *vl, *dl, *uh, *ul;
     const int *g;
     const double *tile;
-    double *partials;
-    int64_t row_begin, row_end, rows_pad, num_tiles, chunk_tiles, num_chunks, num_tb;
+    // Symmetric sweep (sym = 1, the whole event set): for target block b,
+    // every time in blocks < sblk[b] is below every time in b, and every
+    // time in blocks >= eblk[b] is above every time in b.
+    const int *sblk, *eblk;
+    double *prow;  // [num_gc][6][rows_pad]: row sums of the rows against one column group
+    double *pcol;  // [num_gr][3][rows_pad]: background column sums from one row group
+    int row_begin, row_end, rows_pad, num_tiles, num_tb;  // indices below 2^31 (n <= 2^30)
+    int rr, ct;          // target blocks per row group, source tiles per column group
+    int num_gr, num_gc;  // group counts; the grid is num_gr x num_gc workgroups
+    int sym;
+    // Skip mode: every background term of a pair further apart in time than
+    // skip_gap days is exactly zero in FP32.  Tiles that far before a block
+    // sweep the triggering terms only, and in the row sweep (window = 1) tiles
+    // that far after it are not visited.  Without skipping, skip_gap is
+    // infinite and window = 0.
+    int window;
     double omega, inv_st, out_s1, out_s2, out_g1, out_exp;
     double w2;  // omega * log2(e) / time scale: the triggering exponent per scaled day
-    // Skip mode: every background term of a pair further apart in time than
-    // skip_gap days is exactly zero in FP32.  Tiles that far after the block
-    // are not visited (window = 1: each block splits only the tiles it visits
-    // into chunks) and tiles that far before it sweep the triggering terms
-    // only.  Without skipping, skip_gap is infinite and window = 0.
     double skip_gap;
-    int window;
-    // integer geometry (HAWKES_IGEOM): fixed-point coordinates and {q, q^2}
-    const int *xi, *yi, *ti;
-    const double *geo;
 };
 
 // Pair geometry: the scaled squared distance D and the background exponent
-// A = D + dt'^2 in FP32, and the scaled time difference in FP64.
-//  FP64 coordinates: differences and squares in FP64, D and A each rounded once.
-//  int32 fixed-point coordinates (units of q): exact differences, each rounded
-//  once to FP32 (times exactly wherever the background term can be nonzero);
-//  D and A come out in units of q^2.
+// A = D + dt'^2, differences and squares in FP64, D and A each rounded once
+// to FP32.
 __device__ inline void geom_da(double xn, double yn, double tn, double xm, double ym, double tm, float &D, float &A)
 {
     const double dx = xn - xm, dy = yn - ym, dt = tn - tm;
@@ -428,21 +388,10 @@ __device__ inline void geom_da(double xn, double yn, double tn, double xm, doubl
     D = float(d2);
     A = float(fma(dt, dt, d2));
 }
-__device__ inline void geom_da(int xn, int yn, int tn, int xm, int ym, int tm, float &D, float &A)
-{
-    const float dx = float(xn - xm), dy = float(yn - ym), dt = float(tn - tm);
-    D = fmaf(dy, dy, dx * dx);
-    A = fmaf(dt, dt, D);
-}
 __device__ inline float geom_d(double xn, double yn, double xm, double ym)
 {
     const double dx = xn - xm, dy = yn - ym;
     return float(fma(dy, dy, dx * dx));
-}
-__device__ inline float geom_d(int xn, int yn, int xm, int ym)
-{
-    const float dx = float(xn - xm), dy = float(yn - ym);
-    return fmaf(dy, dy, dx * dx);
 }
 // Spatially uniform background: the exponent is the scaled time gap alone,
 // A = dt'^2, so with tied times (integer days) many pairs share one value of
@@ -457,25 +406,56 @@ __device__ inline void geom_da_uni(double xn, double yn, double tn, double xm, d
     A = float(a2);
     Alo = float(a2 - double(A));
 }
-__device__ inline void geom_da_uni(int xn, int yn, int tn, int xm, int ym, int tm, float &D, float &A, float &Alo)
-{
-    const float dx = float(xn - xm), dy = float(yn - ym);
-    D = fmaf(dy, dy, dx * dx);
-    const double dt = double(tn - tm);
-    const double a2 = dt * dt;  // exact: |dt| < 2^31
-    A = float(a2);
-    Alo = float(a2 - double(A));
-}
-__device__ inline double geom_dt(double tn, double tm, double) { return tn - tm; }
-__device__ inline double geom_dt(int tn, int tm, double q) { return double(tn - tm) * q; }
 
-#if HAWKES_IGEOM
-typedef int coord_t;
-#define HK_BG_ARG(A) ((A) * q2f)  // D and A in units of q^2
-#else
-typedef double coord_t;
-#define HK_BG_ARG(A) (A)
-#endif
+// Column sums of the symmetric sweep.  Within each row of 16 lanes, the
+// lanes take the 16 sources of a subgroup in rotation: at step j lane i takes
+// source (i + j) mod 16, and the FP32 column accumulators of a source move
+// with it (row_ror:15: lane i reads lane (i + 1) mod 16 of its row).  After 8
+// steps each lane's accumulator (the row's sum over 8 steps of 2 targets) is
+// kept in FP64 and a new one starts; after 16 steps the first half's FP64 sum
+// of a source sits 8 lanes away from the second half's (row_ror:8).  The four
+// rows take the same sources at the same lane positions and are added by the
+// gfx950 row swaps (permlane16: rows 0+1 and 2+3; permlane32: the halves).
+constexpr int DPP_ROW_ROR8 = 0x128, DPP_ROW_ROR15 = 0x12F;
+template <int CTRL>
+__device__ __forceinline__ int dpp_mov(int v)
+{
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, true);
+}
+__device__ __forceinline__ float row_rotate_f32(float v) { return __int_as_float(dpp_mov<DPP_ROW_ROR15>(__float_as_int(v))); }
+__device__ __forceinline__ double make_f64(unsigned lo, unsigned hi)
+{
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double row_shift8_f64(double v)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    return make_f64(unsigned(dpp_mov<DPP_ROW_ROR8>(int(unsigned(u)))), unsigned(dpp_mov<DPP_ROW_ROR8>(int(unsigned(u >> 32)))));
+}
+__device__ __forceinline__ double sum_rows_f64(double v)
+{
+    unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    auto lo = __builtin_amdgcn_permlane16_swap(unsigned(u), unsigned(u), false, false);
+    auto hi = __builtin_amdgcn_permlane16_swap(unsigned(u >> 32), unsigned(u >> 32), false, false);
+    v = make_f64(lo[0], hi[0]) + make_f64(lo[1], hi[1]);
+    u = (unsigned long long)__double_as_longlong(v);
+    lo = __builtin_amdgcn_permlane32_swap(unsigned(u), unsigned(u), false, false);
+    hi = __builtin_amdgcn_permlane32_swap(unsigned(u >> 32), unsigned(u >> 32), false, false);
+    return make_f64(lo[0], hi[0]) + make_f64(lo[1], hi[1]);
+}
+static_assert(GS == 8, "the column rotation keeps one FP64 partial per 8-source group");
+
+// Direct global-to-LDS load of one dword per lane (global_load_lds_dword):
+// lane l's dword lands at LDS address `wave_base` + 4 l; `wave_base` must be
+// the same for the whole wave.  stage_wait() waits for this wave's
+// outstanding vector memory operations (vmcnt 0), which include these loads.
+typedef __attribute__((address_space(1))) void global_void;
+typedef __attribute__((address_space(3))) void lds_void;
+__device__ __forceinline__ void lds_dma4(const void *src, void *wave_base)
+{
+    __builtin_amdgcn_global_load_lds((global_void *)src, (lds_void *)wave_base, 4, 0, 0);
+}
+__device__ __forceinline__ void stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
 
 // The FP32 fused sweep.  GRAD = false keeps only S0 and G0 (log-likelihood).
 //
@@ -486,8 +466,28 @@ typedef double coord_t;
 //   with t1 = r_m D.  Every FP32 value that many pairs would share is split
 //   hi + lo, and every rounding left is of a value that varies from pair to
 //   pair, so rounding errors average out instead of adding up.
+//
+// A workgroup owns a rectangle: the rr target blocks of row group gr (2 rows
+// per lane each, one block at a time) against the ct source tiles of column
+// group gc.  Row sums stay in registers for a block's sweep over the
+// rectangle's tiles and go to the row partials of column group gc.
+//
+// Symmetric sweep (whole event set).  The background term is symmetric in
+// the pair, so a block pair whose times are strictly ordered is swept once,
+// from the later block: each term b_nm goes to the row sums of n and, as a
+// column sum, to the row sums of m.  The later block's view is then never
+// swept from the earlier block.  Block pairs whose time ranges touch are
+// swept from both sides, with per-tile classes as in the row sweep.  Column
+// sums of a tile are FP32 wave sums (64 lanes x 2 targets), summed over the
+// 4 waves in FP64 by the tile's owner lanes and added to this row group's
+// column partials, which the workgroup alone writes (so every sum keeps a
+// fixed order and results are bitwise reproducible).
+//
+// Row sweep (a row range): every tile is swept for every block (rr = 1,
+// no columns).
+//
 // At least this many waves per SIMD: the register budget the compiler must
-// fit (2 waves = 256 registers per lane).  KT = 2 needs ~166 and runs at 3.
+// fit (2 waves = 256 registers per lane).  KT = 2 needs ~170 and runs at 3.
 #ifndef HAWKES_WAVES_PER_EU
 #define HAWKES_WAVES_PER_EU 2
 #endif
@@ -499,157 +499,203 @@ typedef double coord_t;
 template <bool GRAD, bool UNI>
 __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
 {
-#if !HAWKES_SMEM
-    __shared__ coord_t lx[2][TS], ly[2][TS], lt[2][TS];
-    __shared__ float lrh[2][TS], lrl[2][TS], lvh[2][TS], lvl[2][TS], ld[2][TS], luh[2][TS], lul[2][TS];
-    __shared__ int lg[2][TS];
-#endif
+    // one tile of source records; the fields sit at fixed offsets from each
+    // other, so a source's loads share one address and immediate offsets
+    struct TileRecs {
+        double x[TS], y[TS], t[TS];
+        float rh[TS], rl[TS], vh[TS], vl[TS], d[TS], uh[TS], ul[TS];
+        int g[TS];
+    };
+    __shared__ TileRecs lt2[2];
+    __shared__ float lcol[2][3][NW][TS];  // per-wave column sums of the tile being swept
 
-    const int tid = threadIdx.x;
-#if HAWKES_IGEOM
-    const coord_t *cx = a.xi, *cy = a.yi, *ct = a.ti;
-    const double qnt = a.geo[0], qnt2 = a.geo[1];
-#else
-    const coord_t *cx = a.xs, *cy = a.ys, *ct = a.tsd;
-    const double qnt = 1.0, qnt2 = 1.0;
-#endif
-    const float q2f = float(qnt2);
-    (void)q2f;
-    const int64_t tbr = blockIdx.x / a.num_chunks;
-    const int64_t chunk = blockIdx.x - tbr * a.num_chunks;
-    const int64_t tb = a.num_tb - 1 - tbr;  // latest (most expensive) target blocks first
-    const int64_t i0 = a.row_begin + tb * TB;
-    const int64_t iend = (i0 + TB < a.row_end) ? i0 + TB : a.row_end;
-    const double t_lo = a.t[i0], t_hi = a.t[iend - 1];
-
-    coord_t xn[KT], yn[KT], tsn[KT];
-    double trn[KT];
-    int gn[KT];
-#pragma unroll
-    for (int q = 0; q < KT; ++q) {
-        int64_t i = i0 + tid + q * WG;
-        if (i >= iend)
-            i = iend - 1;
-        xn[q] = cx[i];
-        yn[q] = cy[i];
-        tsn[q] = ct[i];
-        trn[q] = a.t[i];
-        gn[q] = a.g[i];
-    }
-    double acc[KT][6];
-#pragma unroll
-    for (int q = 0; q < KT; ++q)
-#pragma unroll
-        for (int z = 0; z < 6; ++z)
-            acc[q][z] = 0.0;
-
-    int64_t k_end = a.num_tiles, chunk_tiles = a.chunk_tiles;
-    if (a.window) {
-        // first tile that starts more than skip_gap days after the block ends
-        const double limit = t_hi + a.skip_gap;
-        int64_t lo = 0, hi = a.num_tiles;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (a.tile[3 * mid + 0] > limit)
-                hi = mid;
-            else
-                lo = mid + 1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15;
+    const int gr = a.num_gr - 1 - int(blockIdx.x / unsigned(a.num_gc));  // latest row groups first
+    const int gc = int(blockIdx.x % unsigned(a.num_gc));
+    const int b_first = gr * a.rr;
+    const int b_stop = (b_first + a.rr < a.num_tb) ? b_first + a.rr : a.num_tb;
+    const int kg0 = gc * a.ct;
+    const int kg1 = (kg0 + a.ct < a.num_tiles) ? kg0 + a.ct : a.num_tiles;
+    const int64_t stride = a.rows_pad;
+    double *pc = a.pcol + int64_t(gr) * 3 * stride;
+    if (a.sym) {
+        const int kend = KT * a.eblk[b_stop - 1];
+        if (kg0 >= (kend < a.num_tiles ? kend : a.num_tiles))
+            return;  // no block of the row group reaches this column group
+        // this workgroup alone writes the column sums of its tiles for its row group
+        for (int k = kg0; k < kg1; ++k) {
+            const int j = k * TS + tid;
+            pc[j] = 0.0;
+            if (GRAD) {
+                pc[stride + j] = 0.0;
+                pc[2 * stride + j] = 0.0;
+            }
         }
-        k_end = lo;
-        chunk_tiles = (k_end + a.num_chunks - 1) / a.num_chunks;
     }
-    const int64_t k0 = chunk * chunk_tiles;
-    const int64_t k1 = (k0 + chunk_tiles < k_end) ? k0 + chunk_tiles : k_end;
 
-#if !HAWKES_SMEM
-    struct Rec {
-        coord_t x, y, t;
-        float rh, rl, vh, vl, d, uh, ul;
-        int g;
+    // Staging of tile k into LDS buffer buf by direct global-to-LDS loads: each
+    // lane moves one dword per 4-byte array (two per FP64 array), landing at the
+    // wave's base + 4 * lane.  The loads of the next tile run during the sweep;
+    // stage_wait() (this wave's loads done) comes before the barrier that
+    // publishes the tile.
+    auto stage = [&](int k, int buf) {
+        TileRecs &T = lt2[buf];
+        // per-lane offset kept opaque, so that the compiler forms each address
+        // from the array's tile base (scalar) and this offset rather than
+        // holding a per-lane pointer for every array across the loop
+        int o = tid;
+        asm volatile("" : "+v"(o));
+        const int wb = tid & ~63;
+        const unsigned *xs = reinterpret_cast<const unsigned *>(a.xs + k * TS);
+        const unsigned *ys = reinterpret_cast<const unsigned *>(a.ys + k * TS);
+        const unsigned *ts = reinterpret_cast<const unsigned *>(a.tsd + k * TS);
+        lds_dma4(xs + o, reinterpret_cast<unsigned *>(T.x) + wb);
+        lds_dma4(xs + TS + o, reinterpret_cast<unsigned *>(T.x) + TS + wb);
+        lds_dma4(ys + o, reinterpret_cast<unsigned *>(T.y) + wb);
+        lds_dma4(ys + TS + o, reinterpret_cast<unsigned *>(T.y) + TS + wb);
+        lds_dma4(ts + o, reinterpret_cast<unsigned *>(T.t) + wb);
+        lds_dma4(ts + TS + o, reinterpret_cast<unsigned *>(T.t) + TS + wb);
+        const int j0 = k * TS;
+        lds_dma4(a.rh + j0 + o, T.rh + wb);
+        lds_dma4(a.rl + j0 + o, T.rl + wb);
+        lds_dma4(a.vh + j0 + o, T.vh + wb);
+        lds_dma4(a.vl + j0 + o, T.vl + wb);
+        lds_dma4(a.dl + j0 + o, T.d + wb);
+        lds_dma4(a.uh + j0 + o, T.uh + wb);
+        lds_dma4(a.ul + j0 + o, T.ul + wb);
+        lds_dma4(a.g + j0 + o, T.g + wb);
     };
-    auto fetch = [&](int64_t k) {
-        const int64_t j = k * TS + tid;
-        return Rec{cx[j], cy[j], ct[j], a.rh[j], a.rl[j], a.vh[j], a.vl[j], a.dl[j], a.uh[j], a.ul[j], a.g[j]};
-    };
-    auto store = [&](const Rec &r, int buf) {
-        lx[buf][tid] = r.x;
-        ly[buf][tid] = r.y;
-        lt[buf][tid] = r.t;
-        lrh[buf][tid] = r.rh;
-        lrl[buf][tid] = r.rl;
-        lvh[buf][tid] = r.vh;
-        lvl[buf][tid] = r.vl;
-        ld[buf][tid] = r.d;
-        luh[buf][tid] = r.uh;
-        lul[buf][tid] = r.ul;
-        lg[buf][tid] = r.g;
-    };
-#endif
 
-#if !HAWKES_SMEM
-    if (k0 < k1)
-        store(fetch(k0), 0);
-    __syncthreads();
-#endif
+    for (int b = b_first; b < b_stop; ++b) {
+        const int i0 = a.row_begin + b * TB;
+        const int iend = (i0 + TB < a.row_end) ? i0 + TB : a.row_end;
+        const double t_lo = a.t[i0], t_hi = a.t[iend - 1];
 
-    for (int64_t k = k0; k < k1; ++k) {
-#if !HAWKES_SMEM
-        const int buf = int(k - k0) & 1;
-        const bool more = (k + 1 < k1);
-        Rec nxt{};
-        if (more)
-            nxt = fetch(k + 1);  // global loads in flight while this tile is swept
-#endif
-
-        const double first = a.tile[3 * k + 0], last = a.tile[3 * k + 1];
-        const int cls = (last < t_lo) ? CAUSAL : ((first > t_hi) ? ANTI : MIXED);
-        const bool trig_only = (cls == CAUSAL) && (t_lo - last > a.skip_gap);
-
-        // Terms are summed in FP32 over groups of GS = 8 sources and each
-        // group sum is folded into FP64.  Long FP32 running sums would round
-        // away every Gaussian-tail term below half an ulp of the sum, a
-        // systematic loss of ~1e-8 relative; groups of 8 keep it near 3e-10
-        // and equal across the six sums (the gradient combines them with
-        // heavy cancellation, so their errors must match).  Background sums go
-        // straight into the accumulators; the CAUSAL triggering sums keep FP64
-        // tile partials that take the target's time factor at the tile end.
-        double gt[KT][3];
+        // lanes past the block's end take a target far away in space and time:
+        // every one of its terms is exactly 0, so its column terms add nothing
+        double xn[KT], yn[KT], tsn[KT], trn[KT];
+        int gn[KT];
+#pragma unroll
+        for (int q = 0; q < KT; ++q) {
+            const int i = i0 + tid + q * WG;
+            const bool in = i < iend;
+            xn[q] = in ? a.xs[i] : PAD_COORD;
+            yn[q] = in ? a.ys[i] : PAD_COORD;
+            tsn[q] = in ? a.tsd[i] : PAD_TIME;
+            trn[q] = a.t[in ? i : iend - 1];
+            gn[q] = in ? a.g[i] : INT_MAX;
+        }
+        double acc[KT][6];
 #pragma unroll
         for (int q = 0; q < KT; ++q)
-            gt[q][0] = gt[q][1] = gt[q][2] = 0.0;
-
-#if !HAWKES_SMEM
-        const coord_t *sx = lx[buf];
-        const coord_t *sy = ly[buf];
-        const coord_t *st = lt[buf];
-        const float *lrh_ = lrh[buf], *lrl_ = lrl[buf], *lvh_ = lvh[buf], *lvl_ = lvl[buf], *ld_ = ld[buf];
-        const float *luh_ = luh[buf], *lul_ = lul[buf];
-        const int *lg_ = lg[buf];
-#else
-        const int64_t j0 = k * TS;
-        const coord_t *sx = cx + j0;
-        const coord_t *sy = cy + j0;
-        const coord_t *st = ct + j0;
-        const float *lrh_ = a.rh + j0, *lrl_ = a.rl + j0, *lvh_ = a.vh + j0, *lvl_ = a.vl + j0, *ld_ = a.dl + j0;
-        const float *luh_ = a.uh + j0, *lul_ = a.ul + j0;
-        const int *lg_ = a.g + j0;
-#endif
-
-        if (cls != MIXED) {
-            const bool causal = (cls == CAUSAL);
-            const float *srh = lrh_, *srl = lrl_, *svh = lvh_, *svl = lvl_, *sd = ld_;
-            for (int m0 = 0; m0 < TS; m0 += GS) {
-                float f[KT][6];
 #pragma unroll
-                for (int q = 0; q < KT; ++q)
+            for (int z = 0; z < 6; ++z)
+                acc[q][z] = 0.0;
+
+        // tiles [0, k_strict): strictly earlier blocks, swept with column sums;
+        // tiles from k_end on: not visited
+        int k_strict = 0, k_end = a.num_tiles;
+        if (a.sym) {
+            k_strict = KT * a.sblk[b];
+            const int e = KT * a.eblk[b];
+            k_end = (e < a.num_tiles) ? e : a.num_tiles;
+        } else if (a.window) {
+            // first tile that starts more than skip_gap days after the block ends
+            const double limit = t_hi + a.skip_gap;
+            int lo = 0, hi = a.num_tiles;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (a.tile[3 * mid + 0] > limit)
+                    hi = mid;
+                else
+                    lo = mid + 1;
+            }
+            k_end = lo;
+        }
+        const int k0 = kg0;
+        const int k1 = (kg1 < k_end) ? kg1 : k_end;
+
+        if (k0 < k1)
+            stage(k0, 0);
+        stage_wait();
+        __syncthreads();
+
+        for (int k = k0; k < k1; ++k) {
+            const int buf = (k - k0) & 1;
+            if (k + 1 < k1)
+                stage(k + 1, buf ^ 1);  // into the buffer every wave finished reading
+
+            const double first = a.tile[3 * k + 0], last = a.tile[3 * k + 1];
+            const int cls = (last < t_lo) ? CAUSAL : ((first > t_hi) ? ANTI : MIXED);
+            const bool trig_only = (cls == CAUSAL) && (t_lo - last > a.skip_gap);
+            const bool strict = k < k_strict;     // strictly earlier block (so CAUSAL)
+            const bool cols = strict && !trig_only;
+
+            // Terms are summed in FP32 over groups of GS = 8 sources and each
+            // group sum is folded into FP64.  Long FP32 running sums would round
+            // away every Gaussian-tail term below half an ulp of the sum, a
+            // systematic loss of ~1e-8 relative; groups of 8 keep it near 3e-10
+            // and equal across the six sums (the gradient combines them with
+            // heavy cancellation, so their errors must match).  Background sums go
+            // straight into the accumulators; the CAUSAL triggering sums keep FP64
+            // tile partials that take the target's time factor at the tile end.
+            double gt[KT][3];
 #pragma unroll
-                    for (int z = 0; z < 6; ++z)
-                        f[q][z] = 0.0f;
-                if (trig_only) {
-                    HK_UNROLL(HAWKES_UJ)
-                    for (int j = 0; j < GS; ++j) {
-                        const int m = m0 + j;
-                        const coord_t xm = sx[m], ym = sy[m];
+            for (int q = 0; q < KT; ++q)
+                gt[q][0] = gt[q][1] = gt[q][2] = 0.0;
+
+            const TileRecs &T = lt2[buf];
+            const double *sx = T.x, *sy = T.y, *st = T.t;
+            const float *srh = T.rh, *srl = T.rl, *svh = T.vh, *svl = T.vl, *sd = T.d;
+
+            if (cls != MIXED) {
+                const bool causal = (cls == CAUSAL);
+                // column sums (CAUSAL with columns): FP32 over 8 rotation steps, then FP64
+                float e0 = 0.0f, e1 = 0.0f, e2 = 0.0f;
+                double h0 = 0.0, h1 = 0.0, h2 = 0.0;
+                for (int m0 = 0; m0 < TS; m0 += GS) {
+                    float f[KT][6];
+#pragma unroll
+                    for (int q = 0; q < KT; ++q)
+#pragma unroll
+                        for (int z = 0; z < 6; ++z)
+                            f[q][z] = 0.0f;
+                    // background + triggering terms of one source for the lane's targets;
+                    // adds the background terms' sums over those targets (b, b D, b A) to c0..c2
+                    auto causal_pair = [&](int m, float &c0, float &c1, float &c2) {
+                        const double xm = sx[m], ym = sy[m], tm = st[m];
+                        const float rhm = srh[m], rlm = srl[m], vhm = svh[m], vlm = svl[m], dm = sd[m];
+#pragma unroll
+                        for (int q = 0; q < KT; ++q) {
+                            float D, A, Alo = 0.0f;
+                            if (UNI)
+                                geom_da_uni(xn[q], yn[q], tsn[q], xm, ym, tm, D, A, Alo);
+                            else
+                                geom_da(xn[q], yn[q], tsn[q], xm, ym, tm, D, A);
+                            float b = __builtin_amdgcn_exp2f(-A);
+                            if (UNI)
+                                b = fmaf(-LN2F * Alo, b, b);
+                            const float t1 = fmaf(rlm, D, rhm * D);
+                            const float E = __builtin_amdgcn_exp2f(-t1);
+                            const float p = fmaf(vlm, E, vhm * E);
+                            f[q][0] += b;
+                            f[q][3] += p;
+                            c0 += b;
+                            if (GRAD) {
+                                if (!UNI) {
+                                    f[q][1] = fmaf(b, D, f[q][1]);
+                                    c1 = fmaf(b, D, c1);
+                                }
+                                f[q][2] = fmaf(b, A, f[q][2]);
+                                c2 = fmaf(b, A, c2);
+                                f[q][4] = fmaf(p, t1, f[q][4]);
+                                f[q][5] = fmaf(p, dm, f[q][5]);
+                            }
+                        }
+                    };
+                    // triggering terms only (the background terms are exactly zero)
+                    auto trig_pair = [&](int m) {
+                        const double xm = sx[m], ym = sy[m];
                         const float rhm = srh[m], rlm = srl[m], vhm = svh[m], vlm = svl[m], dm = sd[m];
 #pragma unroll
                         for (int q = 0; q < KT; ++q) {
@@ -663,13 +709,134 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
                                 f[q][5] = fmaf(p, dm, f[q][5]);
                             }
                         }
+                    };
+                    const int sub = m0 & ~15, s0 = m0 & 15;
+                    if (trig_only && strict) {
+                        // the sources in the rotated order of the column sweep, so that the
+                        // row sums equal those of the full sweep bit for bit
+                        HK_UNROLL(HAWKES_UJ)
+                        for (int j = 0; j < GS; ++j)
+                            trig_pair(sub + ((li + s0 + j) & 15));
+                    } else if (trig_only) {
+                        HK_UNROLL(HAWKES_UJ)
+                        for (int j = 0; j < GS; ++j)
+                            trig_pair(m0 + j);
+                    } else if (cols) {
+                        // 16-source rotation (row sums as in the plain causal loop): lane i
+                        // takes source sub + ((i + step) mod 16) at step step of the subgroup
+                        HK_UNROLL(HAWKES_UJ)
+                        for (int j = 0; j < GS; ++j) {
+                            float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+                            causal_pair(sub + ((li + s0 + j) & 15), c0, c1, c2);
+                            e0 = row_rotate_f32(e0) + c0;
+                            if (GRAD) {
+                                if (!UNI)
+                                    e1 = row_rotate_f32(e1) + c1;
+                                e2 = row_rotate_f32(e2) + c2;
+                            }
+                        }
+                        if (s0 == 0) {
+                            // first 8 steps: lane i holds source sub + ((i + 7) mod 16)
+                            h0 = double(e0);
+                            h1 = double(e1);
+                            h2 = double(e2);
+                        } else {
+                            // lane i holds source sub + ((i + 15) mod 16), whose first-half sum
+                            // is 8 lanes back; add the halves, then the four rows
+                            double w0 = sum_rows_f64(row_shift8_f64(h0) + double(e0));
+                            double w1 = 0.0, w2 = 0.0;
+                            if (GRAD) {
+                                if (!UNI)
+                                    w1 = sum_rows_f64(row_shift8_f64(h1) + double(e1));
+                                w2 = sum_rows_f64(row_shift8_f64(h2) + double(e2));
+                            }
+                            if (lane < 16) {
+                                const int mc = sub + ((li + 15) & 15);
+                                lcol[buf][0][wave][mc] = float(w0);
+                                if (GRAD) {
+                                    lcol[buf][1][wave][mc] = float(w1);
+                                    lcol[buf][2][wave][mc] = float(w2);
+                                }
+                            }
+                        }
+                        e0 = e1 = e2 = 0.0f;
+                    } else if (causal) {
+                        HK_UNROLL(HAWKES_UJ)
+                        for (int j = 0; j < GS; ++j) {
+                            float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+                            causal_pair(m0 + j, c0, c1, c2);  // column sums unused
+                        }
+                    } else {
+                        HK_UNROLL(HAWKES_UJ)
+                        for (int j = 0; j < GS; ++j) {
+                            const int m = m0 + j;
+                            const double xm = sx[m], ym = sy[m], tm = st[m];
+#pragma unroll
+                            for (int q = 0; q < KT; ++q) {
+                                float D, A, Alo = 0.0f;
+                                if (UNI)
+                                    geom_da_uni(xn[q], yn[q], tsn[q], xm, ym, tm, D, A, Alo);
+                                else
+                                    geom_da(xn[q], yn[q], tsn[q], xm, ym, tm, D, A);
+                                float b = __builtin_amdgcn_exp2f(-A);
+                                if (UNI)
+                                    b = fmaf(-LN2F * Alo, b, b);
+                                f[q][0] += b;
+                                if (GRAD) {
+                                    if (!UNI)
+                                        f[q][1] = fmaf(b, D, f[q][1]);
+                                    f[q][2] = fmaf(b, A, f[q][2]);
+                                }
+                            }
+                        }
                     }
-                } else if (causal) {
-                    HK_UNROLL(HAWKES_UJ)
+#pragma unroll
+                    for (int q = 0; q < KT; ++q) {
+                        if (!trig_only) {
+                            acc[q][0] += double(f[q][0]);
+                            if (GRAD) {
+                                acc[q][1] += double(f[q][1]);
+                                acc[q][2] += double(f[q][2]);
+                            }
+                        }
+                        if (causal) {
+                            gt[q][0] += double(f[q][3]);
+                            if (GRAD) {
+                                gt[q][1] += double(f[q][4]);
+                                gt[q][2] += double(f[q][5]);
+                            }
+                        }
+                    }
+                }
+                if (causal) {
+#pragma unroll
+                    for (int q = 0; q < KT; ++q) {
+                        const double dn = trn[q] - last;
+                        const double fn = exp(-a.omega * dn);
+                        acc[q][3] += fn * gt[q][0];
+                        if (GRAD) {
+                            acc[q][4] += fn * gt[q][1];
+                            acc[q][5] += fn * fma(dn, gt[q][0], gt[q][2]);
+                        }
+                    }
+                }
+            } else {
+                // tiles overlapping the block's time range: per-pair tie-group
+                // masks and the triggering time factor formed per pair in FP64
+                const float *suh = T.uh, *sul = T.ul;
+                const int *sg = T.g;
+                for (int m0 = 0; m0 < TS; m0 += GS) {
+                    float f[KT][6];
+#pragma unroll
+                    for (int q = 0; q < KT; ++q)
+#pragma unroll
+                        for (int z = 0; z < 6; ++z)
+                            f[q][z] = 0.0f;
                     for (int j = 0; j < GS; ++j) {
                         const int m = m0 + j;
-                        const coord_t xm = sx[m], ym = sy[m], tm = st[m];
-                        const float rhm = srh[m], rlm = srl[m], vhm = svh[m], vlm = svl[m], dm = sd[m];
+                        const double xm = sx[m], ym = sy[m], tm = st[m];
+                        const float rhm = srh[m], rlm = srl[m], uhm = suh[m], ulm = sul[m];
+                        const int gm = sg[m];
 #pragma unroll
                         for (int q = 0; q < KT; ++q) {
                             float D, A, Alo = 0.0f;
@@ -677,12 +844,16 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
                                 geom_da_uni(xn[q], yn[q], tsn[q], xm, ym, tm, D, A, Alo);
                             else
                                 geom_da(xn[q], yn[q], tsn[q], xm, ym, tm, D, A);
-                            float b = __builtin_amdgcn_exp2f(-HK_BG_ARG(A));
+                            const double dt = tsn[q] - tm;
+                            float b = __builtin_amdgcn_exp2f(-A);
                             if (UNI)
-                                b = fmaf(-LN2F * HK_BG_ARG(Alo), b, b);
+                                b = fmaf(-LN2F * Alo, b, b);
+                            b = (gm != gn[q]) ? b : 0.0f;
                             const float t1 = fmaf(rlm, D, rhm * D);
-                            const float E = __builtin_amdgcn_exp2f(-t1);
-                            const float p = fmaf(vlm, E, vhm * E);
+                            const float arg = float(fma(a.w2, dt, double(t1)));
+                            const float E = __builtin_amdgcn_exp2f(-arg);
+                            float p = fmaf(ulm, E, uhm * E);
+                            p = (gm < gn[q]) ? p : 0.0f;
                             f[q][0] += b;
                             f[q][3] += p;
                             if (GRAD) {
@@ -690,148 +861,127 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
                                     f[q][1] = fmaf(b, D, f[q][1]);
                                 f[q][2] = fmaf(b, A, f[q][2]);
                                 f[q][4] = fmaf(p, t1, f[q][4]);
-                                f[q][5] = fmaf(p, dm, f[q][5]);
+                                f[q][5] = fmaf(p, float(dt), f[q][5]);
                             }
                         }
                     }
-                } else {
-                    HK_UNROLL(HAWKES_UJ)
-                    for (int j = 0; j < GS; ++j) {
-                        const int m = m0 + j;
-                        const coord_t xm = sx[m], ym = sy[m], tm = st[m];
 #pragma unroll
-                        for (int q = 0; q < KT; ++q) {
-                            float D, A, Alo = 0.0f;
-                            if (UNI)
-                                geom_da_uni(xn[q], yn[q], tsn[q], xm, ym, tm, D, A, Alo);
-                            else
-                                geom_da(xn[q], yn[q], tsn[q], xm, ym, tm, D, A);
-                            float b = __builtin_amdgcn_exp2f(-HK_BG_ARG(A));
-                            if (UNI)
-                                b = fmaf(-LN2F * HK_BG_ARG(Alo), b, b);
-                            f[q][0] += b;
-                            if (GRAD) {
-                                if (!UNI)
-                                    f[q][1] = fmaf(b, D, f[q][1]);
-                                f[q][2] = fmaf(b, A, f[q][2]);
-                            }
-                        }
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < KT; ++q) {
-                    if (!trig_only) {
+                    for (int q = 0; q < KT; ++q) {
                         acc[q][0] += double(f[q][0]);
+                        acc[q][3] += double(f[q][3]);
                         if (GRAD) {
                             acc[q][1] += double(f[q][1]);
                             acc[q][2] += double(f[q][2]);
-                        }
-                    }
-                    if (causal) {
-                        gt[q][0] += double(f[q][3]);
-                        if (GRAD) {
-                            gt[q][1] += double(f[q][4]);
-                            gt[q][2] += double(f[q][5]);
+                            acc[q][4] += double(f[q][4]);
+                            acc[q][5] += double(f[q][5]) * a.inv_st;
                         }
                     }
                 }
             }
-            if (causal) {
+
+            stage_wait();
+            __syncthreads();
+
+            if (cols) {
+                // owner lane of source tid: the four waves' sums in a fixed order
+                const int j = k * TS + tid;
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
-                for (int q = 0; q < KT; ++q) {
-                    const double dn = trn[q] - last;
-                    const double fn = exp(-a.omega * dn);
-                    acc[q][3] += fn * gt[q][0];
+                for (int w = 0; w < NW; ++w) {
+                    s0 += double(lcol[buf][0][w][tid]);
                     if (GRAD) {
-                        acc[q][4] += fn * gt[q][1];
-                        acc[q][5] += fn * fma(dn, gt[q][0], gt[q][2]);
+                        s1 += double(lcol[buf][1][w][tid]);
+                        s2 += double(lcol[buf][2][w][tid]);
                     }
                 }
-            }
-        } else {
-            // tiles overlapping the block's time range: per-pair tie-group
-            // masks and the triggering time factor formed per pair in FP64
-            const float *srh = lrh_, *srl = lrl_, *suh = luh_, *sul = lul_;
-            const int *sg = lg_;
-            for (int m0 = 0; m0 < TS; m0 += GS) {
-                float f[KT][6];
-#pragma unroll
-                for (int q = 0; q < KT; ++q)
-#pragma unroll
-                    for (int z = 0; z < 6; ++z)
-                        f[q][z] = 0.0f;
-                for (int j = 0; j < GS; ++j) {
-                    const int m = m0 + j;
-                    const coord_t xm = sx[m], ym = sy[m], tm = st[m];
-                    const float rhm = srh[m], rlm = srl[m], uhm = suh[m], ulm = sul[m];
-                    const int gm = sg[m];
-#pragma unroll
-                    for (int q = 0; q < KT; ++q) {
-                        float D, A, Alo = 0.0f;
-                        if (UNI)
-                            geom_da_uni(xn[q], yn[q], tsn[q], xm, ym, tm, D, A, Alo);
-                        else
-                            geom_da(xn[q], yn[q], tsn[q], xm, ym, tm, D, A);
-                        const double dt = geom_dt(tsn[q], tm, qnt);
-                        float b = __builtin_amdgcn_exp2f(-HK_BG_ARG(A));
-                        if (UNI)
-                            b = fmaf(-LN2F * HK_BG_ARG(Alo), b, b);
-                        b = (gm != gn[q]) ? b : 0.0f;
-                        const float t1 = fmaf(rlm, D, rhm * D);
-                        const float arg = float(fma(a.w2, dt, double(t1)));
-                        const float E = __builtin_amdgcn_exp2f(-arg);
-                        float p = fmaf(ulm, E, uhm * E);
-                        p = (gm < gn[q]) ? p : 0.0f;
-                        f[q][0] += b;
-                        f[q][3] += p;
-                        if (GRAD) {
-                            if (!UNI)
-                                f[q][1] = fmaf(b, D, f[q][1]);
-                            f[q][2] = fmaf(b, A, f[q][2]);
-                            f[q][4] = fmaf(p, t1, f[q][4]);
-                            f[q][5] = fmaf(p, float(dt), f[q][5]);
-                        }
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < KT; ++q) {
-                    acc[q][0] += double(f[q][0]);
-                    acc[q][3] += double(f[q][3]);
-                    if (GRAD) {
-                        acc[q][1] += double(f[q][1]);
-                        acc[q][2] += double(f[q][2]);
-                        acc[q][4] += double(f[q][4]);
-                        acc[q][5] += double(f[q][5]) * a.inv_st;
-                    }
+                pc[j] += s0 * a.out_exp;
+                if (GRAD) {
+                    if (!UNI)
+                        pc[stride + j] += s1 * (a.out_s1 * a.out_exp);
+                    pc[2 * stride + j] += (s2 - s1) * (a.out_s2 * a.out_exp);
                 }
             }
         }
 
-#if !HAWKES_SMEM
-        if (more)
-            store(nxt, buf ^ 1);
-        __syncthreads();
-#endif
+        // this block's row sums against the column group, in the sums' natural units
+        double *out = a.prow + int64_t(gc) * 6 * stride;
+#pragma unroll
+        for (int q = 0; q < KT; ++q) {
+            const int i = i0 + tid + q * WG;
+            if (i >= iend)
+                continue;
+            const int rr = i - a.row_begin;
+            const double ce = a.out_exp;
+            out[0 * stride + rr] = acc[q][0] * ce;
+            out[3 * stride + rr] = acc[q][3] * ce;
+            if (GRAD) {
+                out[1 * stride + rr] = acc[q][1] * (a.out_s1 * ce);
+                out[2 * stride + rr] = (acc[q][2] - acc[q][1]) * (a.out_s2 * ce);
+                out[4 * stride + rr] = acc[q][4] * (a.out_g1 * ce);
+                out[5 * stride + rr] = acc[q][5] * ce;
+            }
+        }
     }
+}
 
-    // write this chunk's sums in the natural units of the six sums
-    const int64_t stride = a.rows_pad;
-    double *out = a.partials + chunk * 6 * stride;
-#pragma unroll
-    for (int q = 0; q < KT; ++q) {
-        const int64_t i = i0 + tid + q * WG;
-        if (i >= iend)
-            continue;
-        const int64_t rr = i - a.row_begin;
-        const double ce = a.out_exp;
-        out[0 * stride + rr] = acc[q][0] * ce;
-        out[3 * stride + rr] = acc[q][3] * ce;
-        if (GRAD) {
-            out[1 * stride + rr] = acc[q][1] * (a.out_s1 * qnt2 * ce);
-            out[2 * stride + rr] = (acc[q][2] - acc[q][1]) * (a.out_s2 * qnt2 * ce);
-            out[4 * stride + rr] = acc[q][4] * (a.out_g1 * ce);
-            out[5 * stride + rr] = acc[q][5] * ce;
-        }
+// Block bounds of the symmetric sweep: for each target block b, sblk[b] is
+// the first block whose last time is >= b's first time, eblk[b] the first
+// block whose first time is > b's last time (num_tb if none).
+__global__ __launch_bounds__(256) void k_sym_bounds(const double *__restrict__ t, int64_t n, int64_t num_tb,
+                                                    int *__restrict__ sblk, int *__restrict__ eblk)
+{
+    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= num_tb)
+        return;
+    auto first_t = [&](int64_t c) { return t[c * TB]; };
+    auto last_t = [&](int64_t c) {
+        const int64_t e = (c + 1) * TB;
+        return t[(e < n ? e : n) - 1];
+    };
+    const double tl = first_t(b), th = last_t(b);
+    int64_t lo = 0, hi = b;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (last_t(mid) < tl)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    sblk[b] = int(lo);
+    lo = b + 1;
+    hi = num_tb;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (first_t(mid) > th)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    eblk[b] = int(lo);
+}
+
+// Which partial slots hold a row's sums in the symmetric sweep (one
+// workgroup): row group gr has row partials from column groups 0..gchi[gr]
+// (the workgroups that did not exit), and column group gc receives column
+// partials from row groups g0[gc]..num_gr-1.
+__global__ __launch_bounds__(256) void k_sym_plan(const int *__restrict__ eblk, int64_t num_tb, int64_t num_tiles,
+                                                  int rr, int ct, int num_gr, int num_gc, int *__restrict__ gchi,
+                                                  int *__restrict__ g0)
+{
+    __shared__ int hi[MAX_SYM_GROUPS];
+    for (int g = threadIdx.x; g < num_gr; g += blockDim.x) {
+        const int64_t bl = ((int64_t(g) + 1) * rr < num_tb ? (int64_t(g) + 1) * rr : num_tb) - 1;
+        const int64_t e = KT * int64_t(eblk[bl]);
+        const int64_t kend = (e < num_tiles) ? e : num_tiles;
+        hi[g] = int((kend + ct - 1) / ct) - 1;
+        gchi[g] = hi[g];
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < num_gc; c += blockDim.x) {
+        int g = 0;
+        while (g < num_gr && hi[g] < c)
+            ++g;
+        g0[c] = g;
     }
 }
 
@@ -982,12 +1132,15 @@ __global__ __launch_bounds__(WG) void k_pair_f64(PairF64 a)
 struct Fin {
     const double *t, *x, *y, *s;   // raw events (the rescue sweep reads them)
     const int *g;                  // tie-group ids
-    const double *partials;
+    const double *partials;        // row partials [slot][6][rows_pad]
+    const double *pcol;            // symmetric sweep: column partials [row group][3][rows_pad]
+    const int *gchi, *g0;          // symmetric sweep: partial slots of each row and column group
     int *status;                   // [0] flags, [1] rescue count
     int *rescue;                   // rescue list of row offsets
     double *rowvals;               // [7][rows_cap] per-row l_n and gradient terms
     double *lam_out, *comp_out;
-    int64_t n, row_begin, rows, rows_pad, rows_cap, num_chunks;
+    int64_t n, row_begin, rows, rows_pad, rows_cap, num_chunks;  // num_chunks: row sweep slots
+    int sym, rr, ct, num_gr;
     double mu, tau_x, tau_t, xi, h0, omega, c_b, c_g;
     double ax, at, qh;             // 1/(2 tau_x^2), 1/(2 tau_t^2), 1/(2 h0^2)
     double rescue_lambda;          // FP32 rows with lambda below this are recomputed (0: never)
@@ -1034,8 +1187,11 @@ __device__ void row_terms(const Fin &f, const double S[6], double ti, double tN,
     }
 }
 
-// Per-row FP64 finalize: sums the chunk partials in a fixed order, then
-// lambda_n, the floored log, gradient terms and the compensator.
+// Per-row FP64 finalize: sums the partials in a fixed order, then
+// lambda_n, the floored log, gradient terms and the compensator.  Row sweep:
+// every chunk slot.  Symmetric sweep: the row partials of the column groups
+// the row's group reached, then the column partials of the row groups that
+// reached the row's column group.
 template <bool GRAD>
 __global__ __launch_bounds__(256) void k_finalize(Fin f)
 {
@@ -1043,7 +1199,8 @@ __global__ __launch_bounds__(256) void k_finalize(Fin f)
     if (r >= f.rows)
         return;
     double S[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t c = 0; c < f.num_chunks; ++c) {
+    const int64_t nslot = f.sym ? int64_t(f.gchi[(r / TB) / f.rr]) + 1 : f.num_chunks;
+    for (int64_t c = 0; c < nslot; ++c) {
         const double *p = f.partials + c * 6 * f.rows_pad + r;
         S[0] += p[0];
         S[3] += p[3 * f.rows_pad];
@@ -1054,6 +1211,15 @@ __global__ __launch_bounds__(256) void k_finalize(Fin f)
             S[5] += p[5 * f.rows_pad];
         }
     }
+    if (f.sym)
+        for (int64_t g = f.g0[(r / TS) / f.ct]; g < f.num_gr; ++g) {
+            const double *p = f.pcol + g * 3 * f.rows_pad + r;
+            S[0] += p[0];
+            if (GRAD) {
+                S[1] += p[1 * f.rows_pad];
+                S[2] += p[2 * f.rows_pad];
+            }
+        }
     const int64_t i = f.row_begin + r;
     double v[7] = {0, 0, 0, 0, 0, 0, 0}, lam, comp;
     row_terms<GRAD>(f, S, f.t[i], f.t[f.n - 1], v, lam, comp);
@@ -1300,7 +1466,10 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
     const double tau_x = th->tau_x, tau_t = th->tau_t, h0 = th->h0, omega = th->omega;
     const bool uniform = ev->area > 0.0;
     double *partials = at<double>(ws, L.partials);
-    const unsigned pair_blocks = unsigned(P.num_tb * P.num_chunks);
+    unsigned pair_blocks = unsigned(P.num_tb * P.num_chunks);
+    // the symmetric sweep covers the whole event set; a row range takes the row sweep
+    const bool sym = is_fp32(precision) && g_sym_groups > 0 && rb == 0 && re == n;
+    const SymPlan SP = sym ? make_sym_plan(P.num_tb, L.num_tiles, g_sym_groups) : SymPlan{};
 
     if (is_fp32(precision)) {
         StageF32 sc;
@@ -1315,17 +1484,8 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
         float *rh = at<float>(ws, L.rh), *rl = at<float>(ws, L.rl), *vh = at<float>(ws, L.vh);
         float *vl = at<float>(ws, L.vl), *dl = at<float>(ws, L.dl), *uh = at<float>(ws, L.uh);
         float *ul = at<float>(ws, L.ul);
-        int *xi = HAWKES_IGEOM ? at<int>(ws, L.xi) : nullptr;
-        int *yi = HAWKES_IGEOM ? at<int>(ws, L.yi) : nullptr;
-        int *ti = HAWKES_IGEOM ? at<int>(ws, L.ti) : nullptr;
-        if (HAWKES_IGEOM) {
-            hipLaunchKernelGGL(k_extent, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, stream, ev->t, ev->x, ev->y,
-                               n, status);
-            if ((rc = check_launch("extent")) != HAWKES_OK)
-                return rc;
-        }
         hipLaunchKernelGGL(k_stage_f32, dim3(stage_blocks), dim3(256), 0, stream, ev->t, ev->x, ev->y, ev->s, n,
-                           L.n_pad, sc, tile, xs, ys, tsd, rh, rl, vh, vl, dl, uh, ul, status, xi, yi, ti);
+                           L.n_pad, sc, tile, xs, ys, tsd, rh, rl, vh, vl, dl, uh, ul);
         if ((rc = check_launch("stage_f32")) != HAWKES_OK)
             return rc;
         PairF32 a;
@@ -1342,14 +1502,40 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
         a.ul = ul;
         a.g = g;
         a.tile = tile;
-        a.partials = partials;
-        a.row_begin = rb;
-        a.row_end = re;
-        a.rows_pad = P.rows_pad;
-        a.num_tiles = L.num_tiles;
-        a.chunk_tiles = P.chunk_tiles;
-        a.num_chunks = P.num_chunks;
-        a.num_tb = P.num_tb;
+        a.sblk = at<int>(ws, L.sblk);
+        a.eblk = at<int>(ws, L.eblk);
+        a.prow = partials;
+        a.row_begin = int(rb);
+        a.row_end = int(re);
+        a.rows_pad = int(P.rows_pad);
+        a.num_tiles = int(L.num_tiles);
+        a.num_tb = int(P.num_tb);
+        if (sym) {
+            const SymPlan &S = SP;
+            a.rr = S.rr;
+            a.ct = S.ct;
+            a.num_gr = S.num_gr;
+            a.num_gc = S.num_gc;
+            a.pcol = partials + int64_t(S.num_gc) * 6 * P.rows_pad;
+            a.sym = 1;
+            hipLaunchKernelGGL(k_sym_bounds, dim3(unsigned(ceil_div(P.num_tb, 256))), dim3(256), 0, stream, ev->t,
+                               n, P.num_tb, at<int>(ws, L.sblk), at<int>(ws, L.eblk));
+            if ((rc = check_launch("sym_bounds")) != HAWKES_OK)
+                return rc;
+            hipLaunchKernelGGL(k_sym_plan, dim3(1), dim3(256), 0, stream, at<int>(ws, L.eblk), P.num_tb,
+                               L.num_tiles, S.rr, S.ct, S.num_gr, S.num_gc, at<int>(ws, L.gchi),
+                               at<int>(ws, L.g0));
+            if ((rc = check_launch("sym_plan")) != HAWKES_OK)
+                return rc;
+        } else {
+            a.rr = 1;
+            a.ct = int(P.chunk_tiles);
+            a.num_gr = int(P.num_tb);
+            a.num_gc = int(P.num_chunks);
+            a.pcol = partials;  // unused
+            a.sym = 0;
+        }
+        pair_blocks = unsigned(int64_t(a.num_gr) * a.num_gc);
         a.omega = omega;
         a.inv_st = 1.0 / sc.st;
         a.out_s1 = uniform ? 0.0 : 1.0 / (sc.sx * sc.sx);  // D = d^2 sx^2
@@ -1365,10 +1551,6 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
             a.skip_gap = HUGE_VAL;
             a.window = 0;
         }
-        a.xi = xi;
-        a.yi = yi;
-        a.ti = ti;
-        a.geo = reinterpret_cast<const double *>(status) + STATUS_GEO;
         if (g_timing && (rc = record_event(g_ev_start, stream)) != HAWKES_OK)
             return rc;
         if (grad && uniform)
@@ -1440,6 +1622,13 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
     f.rows_pad = P.rows_pad;
     f.rows_cap = L.rows_cap;
     f.num_chunks = P.num_chunks;
+    f.sym = sym ? 1 : 0;
+    f.rr = SP.rr;
+    f.ct = SP.ct;
+    f.num_gr = SP.num_gr;
+    f.pcol = partials + int64_t(SP.num_gc) * 6 * P.rows_pad;
+    f.gchi = is_fp32(precision) ? at<int>(ws, L.gchi) : nullptr;
+    f.g0 = is_fp32(precision) ? at<int>(ws, L.g0) : nullptr;
     f.mu = th->mu;
     f.tau_x = tau_x;
     f.tau_t = tau_t;
@@ -1624,5 +1813,15 @@ extern "C" int hawkes_tune_target_workgroups(int64_t wgs)
     if (wgs < 1 || wgs > MAX_TARGET_WGS)
         return HAWKES_EINVAL;
     g_target_wgs = wgs;
+    return HAWKES_OK;
+}
+
+// Tuning hook (not part of the public header): groups of the symmetric FP32
+// sweep (0 = whole-set calls take the row sweep as well).
+extern "C" int hawkes_tune_symmetric_groups(int64_t groups)
+{
+    if (groups < 0 || groups > MAX_SYM_GROUPS)
+        return HAWKES_EINVAL;
+    g_sym_groups = int(groups);
     return HAWKES_OK;
 }

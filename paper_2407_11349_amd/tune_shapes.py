@@ -5,8 +5,9 @@ HAWKES_KT (target rows per lane), HAWKES_UJ (unroll of the source loop),
 HAWKES_GS (FP32 terms per FP64 fold) and HAWKES_WAVES_PER_EU (register
 budget), into paper_2407_11349_amd/_variants/.  Every shape is timed with the
 library's own HIP-event hook on the 1e6-event, 1200-day workload (FP32
-log-likelihood + gradient, and the FP32 skip mode); its result is compared
-with the first shape's and with the stored FP64 oracle value of that workload.
+log-likelihood + gradient, and the FP32 skip mode), for several group counts
+of the symmetric sweep and for the row sweep; its result is compared with the
+first shape's and with the stored FP64 oracle value of that workload.
 
     python -m paper_2407_11349_amd.tune_shapes build [shape ...]
     python -m paper_2407_11349_amd.tune_shapes time [--n N] [shape ...]
@@ -28,29 +29,15 @@ OUT = Path(__file__).resolve().parent / "_variants"
 # name -> macro definitions
 SHAPES = {
     "kt2": {"HAWKES_KT": 2},
-    "kt4": {"HAWKES_KT": 4},
-    "kt1": {"HAWKES_KT": 1},
-    "kt3": {"HAWKES_KT": 3},
-    "kt2_uj2": {"HAWKES_KT": 2, "HAWKES_UJ": 2},
+    "kt2_uj1": {"HAWKES_KT": 2, "HAWKES_UJ": 1},
     "kt2_uj4": {"HAWKES_KT": 2, "HAWKES_UJ": 4},
-    "kt2_w4": {"HAWKES_KT": 2, "HAWKES_WAVES_PER_EU": 4},
-    "kt2_uj2_w4": {"HAWKES_KT": 2, "HAWKES_UJ": 2, "HAWKES_WAVES_PER_EU": 4},
-    "kt4_nowpe": {"HAWKES_KT": 4, "HAWKES_WAVES_PER_EU": 0},
-    "kt4_w3": {"HAWKES_KT": 4, "HAWKES_WAVES_PER_EU": 3},
-    "kt2_gs16": {"HAWKES_KT": 2, "HAWKES_GS": 16, "HAWKES_UJ": 8},
-    # exact int32 differences of fixed-point coordinates instead of FP64 differences
-    "kt2_ig": {"HAWKES_KT": 2, "HAWKES_IGEOM": 1},
-    "kt2_ig_gs16": {"HAWKES_KT": 2, "HAWKES_IGEOM": 1, "HAWKES_GS": 16, "HAWKES_UJ": 8},
-    "kt4_ig": {"HAWKES_KT": 4, "HAWKES_IGEOM": 1},
-    "kt2_ig_w4": {"HAWKES_KT": 2, "HAWKES_IGEOM": 1, "HAWKES_WAVES_PER_EU": 4},
-    # source records through wave-uniform scalar loads instead of LDS tiles
-    "kt2_smem": {"HAWKES_KT": 2, "HAWKES_SMEM": 1},
-    "kt4_smem": {"HAWKES_KT": 4, "HAWKES_SMEM": 1},
-    "kt2_smem_w4": {"HAWKES_KT": 2, "HAWKES_SMEM": 1, "HAWKES_WAVES_PER_EU": 4},
-    "kt2_smem_uj4": {"HAWKES_KT": 2, "HAWKES_SMEM": 1, "HAWKES_UJ": 4},
-    "kt4_smem_uj4": {"HAWKES_KT": 4, "HAWKES_SMEM": 1, "HAWKES_UJ": 4},
-    "kt2_smem_ig": {"HAWKES_KT": 2, "HAWKES_SMEM": 1, "HAWKES_IGEOM": 1},
+    "kt2_w3": {"HAWKES_KT": 2, "HAWKES_WAVES_PER_EU": 3},
+    "kt1": {"HAWKES_KT": 1},
+    "kt4": {"HAWKES_KT": 4},
 }
+
+# how whole-set FP32 calls are swept: ("sym", groups) or ("rows", target workgroups)
+MODES = [("sym", 96), ("sym", 128), ("sym", 160), ("rows", 32768)]
 
 
 def _build_one(name: str) -> str:
@@ -66,7 +53,7 @@ def _build_one(name: str) -> str:
     lines = res.stderr.splitlines()
     info = []
     for i, line in enumerate(lines):
-        if "Function Name" in line and "k_pair_f32ILb1" in line:
+        if "Function Name" in line and "k_pair_f32ILb1ELb0" in line:
             for l2 in lines[i + 1:i + 14]:
                 m = re.search(r"remark:\s+(.*?)\s*\[-Rpass", l2)
                 if m and m.group(1).split(":")[0] in ("VGPRs", "ScratchSize [bytes/lane]", "Occupancy [waves/SIMD]"):
@@ -104,9 +91,13 @@ def time_shapes(names, n: int) -> None:
         _lib._lib = None
         lib = _lib.load(OUT / f"libhawkes_{name}.so")
         hk.set_timing(True)
-        for wgs in (4096, 16384, 32768):
-            lib.hawkes_tune_target_workgroups(wgs)
-            ws = hk.Workspace(n, "fp32")
+        ws = hk.Workspace(n, "fp32")  # the skip mode uses the same layout
+        for mode, size in MODES:
+            if mode == "sym":
+                lib.hawkes_tune_symmetric_groups(size)
+            else:
+                lib.hawkes_tune_symmetric_groups(0)
+                lib.hawkes_tune_target_workgroups(size)
             ms = []
             for _ in range(3):
                 ll, g = hk.loglik_grad(dev, th, "fp32", ws=ws)
@@ -116,8 +107,7 @@ def time_shapes(names, n: int) -> None:
             ref = ref or (llv, gv)
             dl = abs(llv - ref[0]) / abs(ref[0])
             dg = float(np.max(np.abs(gv - ref[1]) / np.abs(ref[1])))
-            wss = hk.Workspace(n, "fp32_skip")
-            hk.loglik_grad(dev, th, "fp32_skip", ws=wss)
+            hk.loglik_grad(dev, th, "fp32_skip", ws=ws)
             torch.cuda.synchronize()
             skip_ms = hk.last_pair_kernel_ms()
             if gold is not None:
@@ -126,10 +116,11 @@ def time_shapes(names, n: int) -> None:
                 err = f" {el:.1e} | {eg:.1e} |"
             else:
                 err = " - | - |"
-            print(f"| {name} | {wgs} | {min(ms):.1f} | {skip_ms:.1f} | {dl:.1e} | {dg:.1e} |{err}", flush=True)
-            del ws, wss
+            print(f"| {name} | {mode} {size} | {min(ms):.1f} | {skip_ms:.1f} | {dl:.1e} | {dg:.1e} |{err}", flush=True)
+        del ws
         hk.set_timing(False)
         lib.hawkes_tune_target_workgroups(32768)
+        lib.hawkes_tune_symmetric_groups(160)
 
 
 def main() -> None:
@@ -145,7 +136,7 @@ def main() -> None:
     if a.what == "build":
         build(names)
     else:
-        print("| shape | target workgroups | FP32 ms (best of 3) | FP32 skip ms | loglik rel diff | grad rel diff "
+        print("| shape | sweep | FP32 ms (best of 3) | FP32 skip ms | loglik rel diff | grad rel diff "
               "| loglik rel err vs oracle | grad rel err vs oracle |")
         print("|---|---|---|---|---|---|---|---|")
         time_shapes(names, a.n)

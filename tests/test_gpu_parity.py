@@ -222,18 +222,22 @@ def test_bitwise_determinism(prec):
     assert a[0] == b[0] and np.array_equal(a[1], b[1])
 
 
-def test_chunking_does_not_change_results_beyond_rounding():
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_chunking_does_not_change_results_beyond_rounding(prec):
+    """Source chunks of the row sweep (the whole set swept row by row for FP32)."""
     ev = synth.generate(synth.N2K, n=9000, seed=10)
     th = synth.theta_default()
     dev = _dev(ev)
     lib = _lib.load()
     vals = []
     try:
+        assert lib.hawkes_tune_symmetric_groups(0) == 0
         for wgs in (1, 64, 4096, 65536):
             assert lib.hawkes_tune_target_workgroups(wgs) == 0
-            vals.append(_gpu_ll_grad(dev, th, "fp32"))
+            vals.append(_gpu_ll_grad(dev, th, prec))
     finally:
         lib.hawkes_tune_target_workgroups(32768)
+        lib.hawkes_tune_symmetric_groups(160)
     for ll, g in vals[1:]:
         assert ll == pytest.approx(vals[0][0], rel=1e-11)
         np.testing.assert_allclose(g, vals[0][1], rtol=1e-8)

@@ -93,4 +93,6 @@ def test_host_validation_paths(lib):
     assert lib.hawkes_resample_locations(0, None, None, 3, 1, 2, None, None, None) == 0
     assert lib.hawkes_tune_target_workgroups(0) == -1
     assert lib.hawkes_tune_target_workgroups(10**6) == -1
+    assert lib.hawkes_tune_symmetric_groups(-1) == -1
+    assert lib.hawkes_tune_symmetric_groups(161) == -1
     assert lib.hawkes_last_pair_kernel_ms(None) == -1
