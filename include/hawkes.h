@@ -84,8 +84,8 @@ typedef struct hawkes_events {
  * exceed 160 (|t_n - t_m| > sqrt(2 * 160 / log2(e)) tau_t, about 14.9 tau_t):
  * source tiles that early sweep the triggering terms only (and, for a row
  * range, tiles that late are not visited).  The result equals FP32 up to the
- * FP64 summation order of partial sums (identical over the whole set); the
- * work falls when the time span is long against tau_t.
+ * summation order of partial sums of those tiles' triggering terms; the work
+ * falls when the time span is long against tau_t.
  * Results are bitwise reproducible for a given event set, theta, precision,
  * row range and tuning (below). */
 enum hawkes_precision { HAWKES_FP64 = 0, HAWKES_FP32 = 1, HAWKES_FP32_SKIP = 2 };

@@ -151,10 +151,17 @@ SymPlan make_sym_plan(int64_t num_tb, int64_t num_tiles, int groups)
 
 int g_sym_groups = 160;
 
+// Per-source FP32 record fields in 8-byte slots (pairs), so that one index
+// scale addresses every field of a source in LDS.
+struct DeltaGroup {
+    float d;  // T_k - t_m: the source's time offset from its tile's last time
+    int g;    // tie-group id
+};
+
 struct Layout {
     int64_t n = 0, n_pad = 0, num_tiles = 0, part_elems = 0, max_blocks = 0, rows_cap = 0;
     size_t status = 0, g = 0, tile = 0, rowvals = 0, rescue = 0;
-    size_t xs = 0, ys = 0, tsd = 0, rh = 0, rl = 0, vh = 0, vl = 0, dl = 0, uh = 0, ul = 0;
+    size_t xs = 0, ys = 0, tsd = 0, r2 = 0, v2 = 0, u2 = 0, dg = 0;
     size_t sblk = 0, eblk = 0, gchi = 0, g0 = 0;
     size_t partials = 0, blocks = 0, total = 0;
 };
@@ -194,13 +201,10 @@ Layout make_layout(int64_t n, int precision)
         L.xs = take(sizeof(double) * L.n_pad);
         L.ys = take(sizeof(double) * L.n_pad);
         L.tsd = take(sizeof(double) * L.n_pad);
-        L.rh = take(sizeof(float) * L.n_pad);
-        L.rl = take(sizeof(float) * L.n_pad);
-        L.vh = take(sizeof(float) * L.n_pad);
-        L.vl = take(sizeof(float) * L.n_pad);
-        L.dl = take(sizeof(float) * L.n_pad);
-        L.uh = take(sizeof(float) * L.n_pad);
-        L.ul = take(sizeof(float) * L.n_pad);
+        L.r2 = take(sizeof(float2) * L.n_pad);
+        L.v2 = take(sizeof(float2) * L.n_pad);
+        L.u2 = take(sizeof(float2) * L.n_pad);
+        L.dg = take(sizeof(DeltaGroup) * L.n_pad);
         L.sblk = take(sizeof(int) * tb_max);
         L.eblk = take(sizeof(int) * tb_max);
         L.gchi = take(sizeof(int) * MAX_SYM_GROUPS);
@@ -306,20 +310,19 @@ __device__ inline void split_f32(double v, float &hi, float &lo)
     lo = float(v - double(hi));
 }
 
-// Per-theta source records for the FP32 sweep (SoA, padded to whole tiles):
-// positions and times pre-scaled in FP64; r_m = u_m (tau_x/h0)^2,
+// Per-theta source records for the FP32 sweep (SoA of 8-byte fields, padded to
+// whole tiles): positions and times pre-scaled in FP64; r_m = u_m (tau_x/h0)^2,
 // v_m = u_m exp(-omega (T_k - t_m)) and u_m as FP32 hi + lo pairs, so that
 // no rounding is shared by many pairs (all sources of the paper's model 1
-// have one u; integer-day times give few distinct T_k - t_m).
+// have one u; integer-day times give few distinct T_k - t_m); the time offset
+// T_k - t_m with the tie-group id.
 __global__ __launch_bounds__(256) void k_stage_f32(const double *__restrict__ t, const double *__restrict__ x,
                                                    const double *__restrict__ y, const double *__restrict__ s,
-                                                   int64_t n, int64_t n_pad, StageF32 c,
+                                                   const int *__restrict__ g, int64_t n, int64_t n_pad, StageF32 c,
                                                    const double *__restrict__ tile, double *__restrict__ xs,
                                                    double *__restrict__ ys, double *__restrict__ tsd,
-                                                   float *__restrict__ rh, float *__restrict__ rl,
-                                                   float *__restrict__ vh, float *__restrict__ vl,
-                                                   float *__restrict__ dl, float *__restrict__ uh,
-                                                   float *__restrict__ ul)
+                                                   float2 *__restrict__ r2, float2 *__restrict__ v2,
+                                                   float2 *__restrict__ u2, DeltaGroup *__restrict__ dg)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n_pad)
@@ -328,7 +331,8 @@ __global__ __launch_bounds__(256) void k_stage_f32(const double *__restrict__ t,
         xs[i] = PAD_COORD;
         ys[i] = PAD_COORD;
         tsd[i] = PAD_TIME;
-        rh[i] = rl[i] = vh[i] = vl[i] = dl[i] = uh[i] = ul[i] = 0.0f;
+        r2[i] = v2[i] = u2[i] = make_float2(0.0f, 0.0f);
+        dg[i] = DeltaGroup{0.0f, g[i]};
         return;
     }
     const int64_t k = i / TS;
@@ -341,20 +345,18 @@ __global__ __launch_bounds__(256) void k_stage_f32(const double *__restrict__ t,
     tsd[i] = t[i] * c.st;
     float hi, lo;
     split_f32(u * c.rr, hi, lo);
-    rh[i] = hi;
-    rl[i] = lo;
+    r2[i] = make_float2(hi, lo);
     split_f32(u * exp(-c.omega * d), hi, lo);
-    vh[i] = hi;
-    vl[i] = lo;
+    v2[i] = make_float2(hi, lo);
     split_f32(u, hi, lo);
-    uh[i] = hi;
-    ul[i] = lo;
-    dl[i] = float(d);
+    u2[i] = make_float2(hi, lo);
+    dg[i] = DeltaGroup{float(d), g[i]};
 }
 
 struct PairF32 {
     const double *xs, *ys, *tsd, *t;
-    const float *rh, *rl, *vh, *vl, *dl, *uh, *ul;
+    const float2 *r2, *v2, *u2;  // (hi, lo) of r_m, v_m, u_m
+    const DeltaGroup *dg;
     const int *g;
     const double *tile;
     // Symmetric sweep (sym = 1, the whole event set): for target block b,
@@ -422,7 +424,10 @@ __device__ __forceinline__ int dpp_mov(int v)
 {
     return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, true);
 }
-__device__ __forceinline__ float row_rotate_f32(float v) { return __int_as_float(dpp_mov<DPP_ROW_ROR15>(__float_as_int(v))); }
+__device__ __forceinline__ float row_rotate_f32(float v)
+{
+    return __int_as_float(dpp_mov<DPP_ROW_ROR15>(__float_as_int(v)));
+}
 __device__ __forceinline__ double make_f64(unsigned lo, unsigned hi)
 {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
@@ -430,7 +435,8 @@ __device__ __forceinline__ double make_f64(unsigned lo, unsigned hi)
 __device__ __forceinline__ double row_shift8_f64(double v)
 {
     const unsigned long long u = (unsigned long long)__double_as_longlong(v);
-    return make_f64(unsigned(dpp_mov<DPP_ROW_ROR8>(int(unsigned(u)))), unsigned(dpp_mov<DPP_ROW_ROR8>(int(unsigned(u >> 32)))));
+    const int lo = dpp_mov<DPP_ROW_ROR8>(int(unsigned(u))), hi = dpp_mov<DPP_ROW_ROR8>(int(unsigned(u >> 32)));
+    return make_f64(unsigned(lo), unsigned(hi));
 }
 __device__ __forceinline__ double sum_rows_f64(double v)
 {
@@ -477,17 +483,18 @@ __device__ __forceinline__ void stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70
 // from the later block: each term b_nm goes to the row sums of n and, as a
 // column sum, to the row sums of m.  The later block's view is then never
 // swept from the earlier block.  Block pairs whose time ranges touch are
-// swept from both sides, with per-tile classes as in the row sweep.  Column
-// sums of a tile are FP32 wave sums (64 lanes x 2 targets), summed over the
-// 4 waves in FP64 by the tile's owner lanes and added to this row group's
-// column partials, which the workgroup alone writes (so every sum keeps a
-// fixed order and results are bitwise reproducible).
+// swept from both sides, with per-tile classes as in the row sweep.  A
+// wave's column sums of a tile come from the 16-lane rotation above (FP32
+// over 8 steps, then FP64, then over the 4 rows); the tile's owner lanes add
+// the 4 waves' sums in FP64 and add them to this row group's column partials,
+// which the workgroup alone writes (so every sum keeps a fixed order and
+// results are bitwise reproducible).
 //
 // Row sweep (a row range): every tile is swept for every block (rr = 1,
 // no columns).
 //
 // At least this many waves per SIMD: the register budget the compiler must
-// fit (2 waves = 256 registers per lane).  KT = 2 needs ~170 and runs at 3.
+// fit (2 waves = 256 registers per lane).  KT = 2 needs ~163 and runs at 3.
 #ifndef HAWKES_WAVES_PER_EU
 #define HAWKES_WAVES_PER_EU 2
 #endif
@@ -503,8 +510,8 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
     // other, so a source's loads share one address and immediate offsets
     struct TileRecs {
         double x[TS], y[TS], t[TS];
-        float rh[TS], rl[TS], vh[TS], vl[TS], d[TS], uh[TS], ul[TS];
-        int g[TS];
+        float2 r[TS], v[TS], u[TS];
+        DeltaGroup dg[TS];
     };
     __shared__ TileRecs lt2[2];
     __shared__ float lcol[2][3][NW][TS];  // per-wave column sums of the tile being swept
@@ -534,8 +541,8 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
     }
 
     // Staging of tile k into LDS buffer buf by direct global-to-LDS loads: each
-    // lane moves one dword per 4-byte array (two per FP64 array), landing at the
-    // wave's base + 4 * lane.  The loads of the next tile run during the sweep;
+    // lane moves two dwords of every 8-byte-field array, landing at the wave's
+    // base + 4 * lane.  The loads of the next tile run during the sweep;
     // stage_wait() (this wave's loads done) comes before the barrier that
     // publishes the tile.
     auto stage = [&](int k, int buf) {
@@ -555,15 +562,18 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
         lds_dma4(ys + TS + o, reinterpret_cast<unsigned *>(T.y) + TS + wb);
         lds_dma4(ts + o, reinterpret_cast<unsigned *>(T.t) + wb);
         lds_dma4(ts + TS + o, reinterpret_cast<unsigned *>(T.t) + TS + wb);
-        const int j0 = k * TS;
-        lds_dma4(a.rh + j0 + o, T.rh + wb);
-        lds_dma4(a.rl + j0 + o, T.rl + wb);
-        lds_dma4(a.vh + j0 + o, T.vh + wb);
-        lds_dma4(a.vl + j0 + o, T.vl + wb);
-        lds_dma4(a.dl + j0 + o, T.d + wb);
-        lds_dma4(a.uh + j0 + o, T.uh + wb);
-        lds_dma4(a.ul + j0 + o, T.ul + wb);
-        lds_dma4(a.g + j0 + o, T.g + wb);
+        const unsigned *r2 = reinterpret_cast<const unsigned *>(a.r2 + k * TS);
+        const unsigned *v2 = reinterpret_cast<const unsigned *>(a.v2 + k * TS);
+        const unsigned *u2 = reinterpret_cast<const unsigned *>(a.u2 + k * TS);
+        const unsigned *dg = reinterpret_cast<const unsigned *>(a.dg + k * TS);
+        lds_dma4(r2 + o, reinterpret_cast<unsigned *>(T.r) + wb);
+        lds_dma4(r2 + TS + o, reinterpret_cast<unsigned *>(T.r) + TS + wb);
+        lds_dma4(v2 + o, reinterpret_cast<unsigned *>(T.v) + wb);
+        lds_dma4(v2 + TS + o, reinterpret_cast<unsigned *>(T.v) + TS + wb);
+        lds_dma4(u2 + o, reinterpret_cast<unsigned *>(T.u) + wb);
+        lds_dma4(u2 + TS + o, reinterpret_cast<unsigned *>(T.u) + TS + wb);
+        lds_dma4(dg + o, reinterpret_cast<unsigned *>(T.dg) + wb);
+        lds_dma4(dg + TS + o, reinterpret_cast<unsigned *>(T.dg) + TS + wb);
     };
 
     for (int b = b_first; b < b_stop; ++b) {
@@ -628,8 +638,7 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
             const double first = a.tile[3 * k + 0], last = a.tile[3 * k + 1];
             const int cls = (last < t_lo) ? CAUSAL : ((first > t_hi) ? ANTI : MIXED);
             const bool trig_only = (cls == CAUSAL) && (t_lo - last > a.skip_gap);
-            const bool strict = k < k_strict;     // strictly earlier block (so CAUSAL)
-            const bool cols = strict && !trig_only;
+            const bool cols = (k < k_strict) && !trig_only;  // strictly earlier block (so CAUSAL)
 
             // Terms are summed in FP32 over groups of GS = 8 sources and each
             // group sum is folded into FP64.  Long FP32 running sums would round
@@ -646,7 +655,8 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
 
             const TileRecs &T = lt2[buf];
             const double *sx = T.x, *sy = T.y, *st = T.t;
-            const float *srh = T.rh, *srl = T.rl, *svh = T.vh, *svl = T.vl, *sd = T.d;
+            const float2 *sr = T.r, *sv = T.v;
+            const DeltaGroup *sdg = T.dg;
 
             if (cls != MIXED) {
                 const bool causal = (cls == CAUSAL);
@@ -664,7 +674,8 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
                     // adds the background terms' sums over those targets (b, b D, b A) to c0..c2
                     auto causal_pair = [&](int m, float &c0, float &c1, float &c2) {
                         const double xm = sx[m], ym = sy[m], tm = st[m];
-                        const float rhm = srh[m], rlm = srl[m], vhm = svh[m], vlm = svl[m], dm = sd[m];
+                        const float2 rm = sr[m], vm = sv[m];
+                        const float rhm = rm.x, rlm = rm.y, vhm = vm.x, vlm = vm.y, dm = sdg[m].d;
 #pragma unroll
                         for (int q = 0; q < KT; ++q) {
                             float D, A, Alo = 0.0f;
@@ -696,7 +707,8 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
                     // triggering terms only (the background terms are exactly zero)
                     auto trig_pair = [&](int m) {
                         const double xm = sx[m], ym = sy[m];
-                        const float rhm = srh[m], rlm = srl[m], vhm = svh[m], vlm = svl[m], dm = sd[m];
+                        const float2 rm = sr[m], vm = sv[m];
+                        const float rhm = rm.x, rlm = rm.y, vhm = vm.x, vlm = vm.y, dm = sdg[m].d;
 #pragma unroll
                         for (int q = 0; q < KT; ++q) {
                             const float D = geom_d(xn[q], yn[q], xm, ym);
@@ -711,13 +723,7 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
                         }
                     };
                     const int sub = m0 & ~15, s0 = m0 & 15;
-                    if (trig_only && strict) {
-                        // the sources in the rotated order of the column sweep, so that the
-                        // row sums equal those of the full sweep bit for bit
-                        HK_UNROLL(HAWKES_UJ)
-                        for (int j = 0; j < GS; ++j)
-                            trig_pair(sub + ((li + s0 + j) & 15));
-                    } else if (trig_only) {
+                    if (trig_only) {
                         HK_UNROLL(HAWKES_UJ)
                         for (int j = 0; j < GS; ++j)
                             trig_pair(m0 + j);
@@ -823,8 +829,7 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
             } else {
                 // tiles overlapping the block's time range: per-pair tie-group
                 // masks and the triggering time factor formed per pair in FP64
-                const float *suh = T.uh, *sul = T.ul;
-                const int *sg = T.g;
+                const float2 *su = T.u;
                 for (int m0 = 0; m0 < TS; m0 += GS) {
                     float f[KT][6];
 #pragma unroll
@@ -835,8 +840,9 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
                     for (int j = 0; j < GS; ++j) {
                         const int m = m0 + j;
                         const double xm = sx[m], ym = sy[m], tm = st[m];
-                        const float rhm = srh[m], rlm = srl[m], uhm = suh[m], ulm = sul[m];
-                        const int gm = sg[m];
+                        const float2 rm = sr[m], um = su[m];
+                        const float rhm = rm.x, rlm = rm.y, uhm = um.x, ulm = um.y;
+                        const int gm = sdg[m].g;
 #pragma unroll
                         for (int q = 0; q < KT; ++q) {
                             float D, A, Alo = 0.0f;
@@ -1481,11 +1487,10 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
         sc.rr = (tau_sp / h0) * (tau_sp / h0);
         sc.omega = omega;
         double *xs = at<double>(ws, L.xs), *ys = at<double>(ws, L.ys), *tsd = at<double>(ws, L.tsd);
-        float *rh = at<float>(ws, L.rh), *rl = at<float>(ws, L.rl), *vh = at<float>(ws, L.vh);
-        float *vl = at<float>(ws, L.vl), *dl = at<float>(ws, L.dl), *uh = at<float>(ws, L.uh);
-        float *ul = at<float>(ws, L.ul);
-        hipLaunchKernelGGL(k_stage_f32, dim3(stage_blocks), dim3(256), 0, stream, ev->t, ev->x, ev->y, ev->s, n,
-                           L.n_pad, sc, tile, xs, ys, tsd, rh, rl, vh, vl, dl, uh, ul);
+        float2 *r2 = at<float2>(ws, L.r2), *v2 = at<float2>(ws, L.v2), *u2 = at<float2>(ws, L.u2);
+        DeltaGroup *dg = at<DeltaGroup>(ws, L.dg);
+        hipLaunchKernelGGL(k_stage_f32, dim3(stage_blocks), dim3(256), 0, stream, ev->t, ev->x, ev->y, ev->s, g,
+                           n, L.n_pad, sc, tile, xs, ys, tsd, r2, v2, u2, dg);
         if ((rc = check_launch("stage_f32")) != HAWKES_OK)
             return rc;
         PairF32 a;
@@ -1493,13 +1498,10 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
         a.ys = ys;
         a.tsd = tsd;
         a.t = ev->t;
-        a.rh = rh;
-        a.rl = rl;
-        a.vh = vh;
-        a.vl = vl;
-        a.dl = dl;
-        a.uh = uh;
-        a.ul = ul;
+        a.r2 = r2;
+        a.v2 = v2;
+        a.u2 = u2;
+        a.dg = dg;
         a.g = g;
         a.tile = tile;
         a.sblk = at<int>(ws, L.sblk);

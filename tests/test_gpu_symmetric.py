@@ -107,15 +107,18 @@ def test_block_edges_per_event(n, prec):
 @pytest.mark.parametrize("area", [0.0, 1e6])
 def test_skip_equals_full_on_the_symmetric_sweep(area):
     """Over the whole set both modes use the same partition, and the terms the skip mode
-    leaves out are exact zeros: the results are bitwise equal."""
+    leaves out are exact zeros; only the order in which the far tiles' triggering terms are
+    summed differs (the full sweep takes them in the column rotation), so the results agree
+    to rounding of those terms, which are below e^(-omega * 104 d) = 1e-9 of the rates."""
     t, ev = _events("sparse", 30000, 12)
     th = synth.theta_default()
     dev = hk.DeviceEvents.from_arrays(t, ev.x, ev.y, ev.s, area=area)
     full = _run(dev, th, "fp32")
     skip = _run(dev, th, "fp32_skip")
-    assert skip[0] == full[0]
-    for a, b in zip(skip[1:], full[1:]):
-        assert np.array_equal(a, b)
+    assert skip[0] == pytest.approx(full[0], rel=1e-14)
+    np.testing.assert_allclose(skip[1], full[1], rtol=1e-11)
+    np.testing.assert_allclose(skip[2], full[2], rtol=1e-12)
+    assert np.array_equal(skip[3], full[3])
 
 
 def test_uniform_background_ties_against_row_sweep():
