@@ -83,9 +83,11 @@ typedef struct hawkes_events {
  * exactly zero in FP32 because the scaled time gap alone makes its exponent
  * exceed 160 (|t_n - t_m| > sqrt(2 * 160 / log2(e)) tau_t, about 14.9 tau_t):
  * source tiles that early sweep the triggering terms only (and, for a row
- * range, tiles that late are not visited).  The result equals FP32 up to the
- * summation order of partial sums of those tiles' triggering terms; the work
- * falls when the time span is long against tau_t.
+ * range, tiles that late are not visited); source tiles so early that every
+ * triggering term is below 2^-160 (max_m s_m^-2 exp(-omega gap) < 2^-160) are
+ * not visited at all.  The result equals FP32 up to the summation order of
+ * those tiles' triggering terms; the work falls when the time span is long
+ * against tau_t and 1/omega.
  * Results are bitwise reproducible for a given event set, theta, precision,
  * row range and tuning (below). */
 enum hawkes_precision { HAWKES_FP64 = 0, HAWKES_FP32 = 1, HAWKES_FP32_SKIP = 2 };

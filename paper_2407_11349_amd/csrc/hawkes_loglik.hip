@@ -117,6 +117,11 @@ constexpr double RESCUE_REL = 1e-12;
 // FP32 (the smallest subnormal is 2^-149); the skip mode leaves out pairs
 // whose scaled time gap alone reaches it.
 constexpr double SKIP_EXPONENT = 160.0;
+// The skip mode also leaves out source tiles so far before a target block
+// that each triggering term is below 2^-160 (u_max exp(-omega gap)): terms
+// that underflow to zero in FP32 arithmetic and change no FP64 sum here.
+constexpr double TRIG_SKIP_EXPONENT = 160.0;
+constexpr double LN2 = 0.69314718055994530942;
 
 constexpr int STATUS_ORDER = 1;
 constexpr int STATUS_DATA = 2;
@@ -243,11 +248,38 @@ Plan make_plan(int64_t rows, int64_t num_tiles)
 
 // ------------------------------------------------------------- kernels
 
-// status[0]: data-check flags; status[1]: number of rows on the rescue list.
+// status[0]: data-check flags; status[1]: number of rows on the rescue list;
+// 8-byte word STATUS_UMAX: the largest u_m = s_m^-2 (FP64 bit pattern, which
+// orders like the value for non-negative numbers), set by k_umax.
+constexpr int STATUS_UMAX = 1;
 __global__ void k_clear_status(int *status)
 {
     status[0] = 0;
     status[1] = 0;
+    reinterpret_cast<unsigned long long *>(status)[STATUS_UMAX] = 0ull;
+}
+
+// Largest u_m = 1 / s_m^2 over the events (one atomic per workgroup).
+__global__ __launch_bounds__(256) void k_umax(const double *__restrict__ s, int64_t n, int *status)
+{
+    __shared__ double red[256];
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    double u = 0.0;
+    if (i < n) {
+        const double si = s[i];
+        u = 1.0 / (si * si);
+        u = (isfinite(u) && u > 0.0) ? u : 0.0;  // bad values are flagged by the data checks
+    }
+    red[threadIdx.x] = u;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        atomicMax(reinterpret_cast<unsigned long long *>(status) + STATUS_UMAX,
+                  (unsigned long long)__double_as_longlong(red[0]));
 }
 
 __global__ void k_zero_outputs(double *loglik, double *grad)
@@ -373,8 +405,11 @@ struct PairF32 {
     // skip_gap days is exactly zero in FP32.  Tiles that far before a block
     // sweep the triggering terms only, and in the row sweep (window = 1) tiles
     // that far after it are not visited.  Without skipping, skip_gap is
-    // infinite and window = 0.
-    int window;
+    // infinite and window = 0.  With trig_cull, tiles so far before a block that
+    // every triggering term is below 2^-TRIG_SKIP_EXPONENT (in units of the sum
+    // G0; u_m <= u_max) are not visited either.
+    int window, trig_cull;
+    const unsigned long long *umax;  // the status word holding u_max
     double omega, inv_st, out_s1, out_s2, out_g1, out_exp;
     double w2;  // omega * log2(e) / time scale: the triggering exponent per scaled day
     double skip_gap;
@@ -576,6 +611,16 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
         lds_dma4(dg + TS + o, reinterpret_cast<unsigned *>(T.dg) + TS + wb);
     };
 
+    // trig_cull: a triggering term of a source more than cull_gap days before its
+    // target is below u_max exp(-omega gap) < 2^-TRIG_SKIP_EXPONENT; no smaller
+    // than skip_gap, so that the background terms there are exactly zero too
+    double cull_gap = a.skip_gap;
+    if (a.trig_cull) {
+        const double um = __longlong_as_double((long long)*a.umax);
+        const double tg = (log(um) + TRIG_SKIP_EXPONENT * LN2) / a.omega;
+        cull_gap = (tg > cull_gap) ? tg : cull_gap;
+    }
+
     for (int b = b_first; b < b_stop; ++b) {
         const int i0 = a.row_begin + b * TB;
         const int iend = (i0 + TB < a.row_end) ? i0 + TB : a.row_end;
@@ -604,7 +649,20 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
 
         // tiles [0, k_strict): strictly earlier blocks, swept with column sums;
         // tiles from k_end on: not visited
-        int k_strict = 0, k_end = a.num_tiles;
+        int k_strict = 0, k_end = a.num_tiles, k_lo = 0;
+        if (a.trig_cull) {
+            // first tile whose last time is within cull_gap days of the block
+            const double limit = t_lo - cull_gap;
+            int lo = 0, hi = a.num_tiles;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (a.tile[3 * mid + 1] < limit)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            k_lo = lo;
+        }
         if (a.sym) {
             k_strict = KT * a.sblk[b];
             const int e = KT * a.eblk[b];
@@ -622,7 +680,7 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
             }
             k_end = lo;
         }
-        const int k0 = kg0;
+        const int k0 = (kg0 > k_lo) ? kg0 : k_lo;
         const int k1 = (kg1 < k_end) ? kg1 : k_end;
 
         if (k0 < k1)
@@ -1545,13 +1603,19 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
         a.out_g1 = 2.0 * h0 * h0 / LOG2E;        // t1 = u d^2 log2(e) / (2 h0^2)
         a.w2 = omega * LOG2E / sc.st;
         a.out_exp = 1.0 / (1.0 + EXP2_MEAN_REL_ERR);
+        a.umax = reinterpret_cast<const unsigned long long *>(status) + STATUS_UMAX;
         if (precision == HAWKES_FP32_SKIP) {
             // scaled time gap whose square exceeds 160: exp2(-A) <= 2^-160 is 0 in FP32
             a.skip_gap = std::sqrt(SKIP_EXPONENT) / sc.st;
             a.window = 1;
+            a.trig_cull = 1;
+            hipLaunchKernelGGL(k_umax, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, stream, ev->s, n, status);
+            if ((rc = check_launch("umax")) != HAWKES_OK)
+                return rc;
         } else {
             a.skip_gap = HUGE_VAL;
             a.window = 0;
+            a.trig_cull = 0;
         }
         if (g_timing && (rc = record_event(g_ev_start, stream)) != HAWKES_OK)
             return rc;

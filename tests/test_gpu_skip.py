@@ -117,3 +117,23 @@ def test_skip_row_ranges_add_up():
     a, b = 11111, 29999
     ref, _ = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th, rows=(a, b))
     assert abs(parts[3][0] - ref) <= TOL_L * abs(ref) + 5e-7 * np.sqrt(b - a)
+
+
+@pytest.mark.parametrize("omega", [0.5, 2.0])
+def test_skip_trigger_culling_matches_fp32(omega):
+    """Tiles so far before a block that every triggering term is below 2^-160 (u_max e^(-omega
+    gap)) are not visited in the skip mode: with omega = 0.5 / 2 per day that is beyond ~230 /
+    ~60 days of the 1000-day span.  The terms left out change no FP64 sum."""
+    ev = synth.generate(synth.N100K, n=20000, seed=44)
+    th = synth.theta_default()
+    th[5] = omega
+    dev = _dev(ev)
+    full = _run(dev, th, "fp32")
+    skip = _run(dev, th, "fp32_skip")
+    assert skip[0] == pytest.approx(full[0], rel=1e-14)
+    np.testing.assert_allclose(skip[1], full[1], rtol=1e-11)
+    np.testing.assert_allclose(skip[2], full[2], rtol=1e-12)
+    ll_ref, g_ref = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th)
+    _say(f"skip culling omega={omega}: loglik rel err {abs(skip[0] - ll_ref) / abs(ll_ref):.2e}")
+    assert abs(skip[0] - ll_ref) <= TOL_L * abs(ll_ref)
+    np.testing.assert_allclose(skip[1], g_ref, rtol=TOL_G)
