@@ -185,7 +185,7 @@ Layout make_layout(int64_t n, int precision)
     if (slots > MAX_TARGET_WGS + tb_max)
         slots = MAX_TARGET_WGS + tb_max;
     L.part_elems = slots * TB * 6;
-    if (is_fp32(precision)) {
+    {
         // symmetric sweep at the largest group count: 6 row and 3 column sums per group
         const SymPlan S = make_sym_plan(tb_max, L.num_tiles, MAX_SYM_GROUPS);
         const int64_t sym_elems = (6 * int64_t(S.num_gc) + 3 * int64_t(S.num_gr)) * L.rows_cap;
@@ -210,11 +210,11 @@ Layout make_layout(int64_t n, int precision)
         L.v2 = take(sizeof(float2) * L.n_pad);
         L.u2 = take(sizeof(float2) * L.n_pad);
         L.dg = take(sizeof(DeltaGroup) * L.n_pad);
-        L.sblk = take(sizeof(int) * tb_max);
-        L.eblk = take(sizeof(int) * tb_max);
-        L.gchi = take(sizeof(int) * MAX_SYM_GROUPS);
-        L.g0 = take(sizeof(int) * MAX_SYM_GROUPS);
     }
+    L.sblk = take(sizeof(int) * tb_max);
+    L.eblk = take(sizeof(int) * tb_max);
+    L.gchi = take(sizeof(int) * MAX_SYM_GROUPS);
+    L.g0 = take(sizeof(int) * MAX_SYM_GROUPS);
     L.partials = take(sizeof(double) * L.part_elems);
     L.blocks = take(sizeof(double) * 7 * L.max_blocks);
     L.rowvals = take(sizeof(double) * 7 * L.rows_cap);
@@ -1053,49 +1053,56 @@ struct PairF64 {
     const double *t, *x, *y, *s;
     const int *g;
     const double *tile;
-    double *partials;
-    int64_t n, row_begin, row_end, rows_pad, num_tiles, chunk_tiles, num_chunks, num_tb;
+    const int *sblk, *eblk;  // symmetric sweep: block order bounds (as in PairF32)
+    double *prow, *pcol;     // row partials [num_gc][6][rows_pad], column partials [num_gr][3][rows_pad]
+    int n, row_begin, row_end, rows_pad, num_tiles, num_tb;
+    int rr, ct, num_gr, num_gc, sym;
     double ax, at, qh, omega;  // 1/(2 tau_x^2), 1/(2 tau_t^2), 1/(2 h0^2), omega
 };
 
-// The FP64 sweep: every pair term in FP64 with the direct formulas.
+__device__ __forceinline__ double row_rotate_f64(double v)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const int lo = dpp_mov<DPP_ROW_ROR15>(int(unsigned(u))), hi = dpp_mov<DPP_ROW_ROR15>(int(unsigned(u >> 32)));
+    return make_f64(unsigned(lo), unsigned(hi));
+}
+
+// The FP64 sweep: every pair term in FP64 with the direct formulas, on the
+// same work decomposition as the FP32 sweep (row groups x column groups; over
+// the whole event set the symmetric sweep, with the background column sums of
+// a strictly earlier tile carried by the 16-lane rotation in FP64, summed over
+// the 4 rows and the 4 waves and added to this row group's column partials).
 template <bool GRAD>
 __global__ __launch_bounds__(WG) void k_pair_f64(PairF64 a)
 {
     __shared__ double lx[2][TS], ly[2][TS], lt[2][TS], lu[2][TS];
     __shared__ int lg[2][TS];
+    __shared__ double lcol[3][NW][TS];  // per-wave column sums of the tile just swept
 
-    const int tid = threadIdx.x;
-    const int64_t tbr = blockIdx.x / a.num_chunks;
-    const int64_t chunk = blockIdx.x - tbr * a.num_chunks;
-    const int64_t tb = a.num_tb - 1 - tbr;
-    const int64_t i0 = a.row_begin + tb * TB;
-    const int64_t iend = (i0 + TB < a.row_end) ? i0 + TB : a.row_end;
-    const double t_lo = a.t[i0], t_hi = a.t[iend - 1];
-
-    double xn[KT], yn[KT], tn[KT];
-    int gn[KT];
-#pragma unroll
-    for (int q = 0; q < KT; ++q) {
-        int64_t i = i0 + tid + q * WG;
-        if (i >= iend)
-            i = iend - 1;
-        xn[q] = a.x[i];
-        yn[q] = a.y[i];
-        tn[q] = a.t[i];
-        gn[q] = a.g[i];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15;
+    const int gr = a.num_gr - 1 - int(blockIdx.x / unsigned(a.num_gc));  // latest row groups first
+    const int gc = int(blockIdx.x % unsigned(a.num_gc));
+    const int b_first = gr * a.rr;
+    const int b_stop = (b_first + a.rr < a.num_tb) ? b_first + a.rr : a.num_tb;
+    const int kg0 = gc * a.ct;
+    const int kg1 = (kg0 + a.ct < a.num_tiles) ? kg0 + a.ct : a.num_tiles;
+    const int64_t stride = a.rows_pad;
+    double *pc = a.pcol + int64_t(gr) * 3 * stride;
+    if (a.sym) {
+        const int kend = KT * a.eblk[b_stop - 1];
+        if (kg0 >= (kend < a.num_tiles ? kend : a.num_tiles))
+            return;  // no block of the row group reaches this column group
+        for (int k = kg0; k < kg1; ++k) {
+            const int j = k * TS + tid;
+            pc[j] = 0.0;
+            if (GRAD) {
+                pc[stride + j] = 0.0;
+                pc[2 * stride + j] = 0.0;
+            }
+        }
     }
-    double acc[KT][6];
-#pragma unroll
-    for (int q = 0; q < KT; ++q)
-#pragma unroll
-        for (int z = 0; z < 6; ++z)
-            acc[q][z] = 0.0;
 
-    const int64_t k0 = chunk * a.chunk_tiles;
-    const int64_t k1 = (k0 + a.chunk_tiles < a.num_tiles) ? k0 + a.chunk_tiles : a.num_tiles;
-
-    auto fetch = [&](int64_t j, double &fx, double &fy, double &ft, double &fu, int &fg) {
+    auto fetch = [&](int j, double &fx, double &fy, double &ft, double &fu, int &fg) {
         if (j < a.n) {
             fx = a.x[j];
             fy = a.y[j];
@@ -1111,84 +1118,177 @@ __global__ __launch_bounds__(WG) void k_pair_f64(PairF64 a)
             fg = INT_MAX;
         }
     };
-    {
-        double fx, fy, ft, fu;
-        int fg;
-        fetch(k0 * TS + tid, fx, fy, ft, fu, fg);
-        lx[0][tid] = fx;
-        ly[0][tid] = fy;
-        lt[0][tid] = ft;
-        lu[0][tid] = fu;
-        lg[0][tid] = fg;
-    }
-    __syncthreads();
 
-    for (int64_t k = k0; k < k1; ++k) {
-        const int buf = int(k - k0) & 1;
-        const bool more = (k + 1 < k1);
-        double px = 0, py = 0, pt = 0, pu = 0;
-        int pg = 0;
-        if (more)
-            fetch((k + 1) * TS + tid, px, py, pt, pu, pg);
-
-        const double first = a.tile[3 * k + 0], last = a.tile[3 * k + 1];
-        const int cls = (last < t_lo) ? CAUSAL : ((first > t_hi) ? ANTI : MIXED);
-        const int mlen = (k * TS + TS <= a.n) ? TS : int(a.n - k * TS);
-
-        for (int m = 0; m < mlen; ++m) {
-            const double xm = lx[buf][m], ym = ly[buf][m], tm = lt[buf][m], um = lu[buf][m];
-            const int gm = lg[buf][m];
+    for (int b = b_first; b < b_stop; ++b) {
+        const int i0 = a.row_begin + b * TB;
+        const int iend = (i0 + TB < a.row_end) ? i0 + TB : a.row_end;
+        const double t_lo = a.t[i0], t_hi = a.t[iend - 1];
+        // lanes past the block's end take a target far away: all of its terms are 0
+        double xn[KT], yn[KT], tn[KT];
+        int gn[KT];
 #pragma unroll
-            for (int q = 0; q < KT; ++q) {
-                const double dx = xn[q] - xm, dy = yn[q] - ym;
-                const double d2 = dx * dx + dy * dy;
-                const double dt = tn[q] - tm;
-                const bool use_b = (cls != MIXED) || (gm != gn[q]);
-                const bool use_g = (cls == CAUSAL) || (cls == MIXED && gm < gn[q]);
-                if (use_b) {
-                    const double b = exp(-(a.ax * d2 + a.at * dt * dt));
-                    acc[q][0] += b;
-                    if (GRAD) {
-                        acc[q][1] += b * d2;
-                        acc[q][2] += b * dt * dt;
-                    }
-                }
-                if (use_g) {
-                    const double e = um * exp(-(um * a.qh * d2 + a.omega * dt));
-                    acc[q][3] += e;
-                    if (GRAD) {
-                        acc[q][4] += e * (um * d2);
-                        acc[q][5] += e * dt;
-                    }
-                }
-            }
+        for (int q = 0; q < KT; ++q) {
+            const int i = i0 + tid + q * WG;
+            const bool in = i < iend;
+            xn[q] = in ? a.x[i] : PAD_COORD;
+            yn[q] = in ? a.y[i] : PAD_COORD;
+            tn[q] = in ? a.t[i] : PAD_TIME;
+            gn[q] = in ? a.g[i] : INT_MAX;
         }
-        if (more) {
-            const int nb = buf ^ 1;
-            lx[nb][tid] = px;
-            ly[nb][tid] = py;
-            lt[nb][tid] = pt;
-            lu[nb][tid] = pu;
-            lg[nb][tid] = pg;
+        double acc[KT][6];
+#pragma unroll
+        for (int q = 0; q < KT; ++q)
+#pragma unroll
+            for (int z = 0; z < 6; ++z)
+                acc[q][z] = 0.0;
+
+        int k_strict = 0, k_end = a.num_tiles;
+        if (a.sym) {
+            k_strict = KT * a.sblk[b];
+            const int e = KT * a.eblk[b];
+            k_end = (e < a.num_tiles) ? e : a.num_tiles;
+        }
+        const int k0 = kg0;
+        const int k1 = (kg1 < k_end) ? kg1 : k_end;
+
+        if (k0 < k1) {
+            double fx, fy, ft, fu;
+            int fg;
+            fetch(k0 * TS + tid, fx, fy, ft, fu, fg);
+            lx[0][tid] = fx;
+            ly[0][tid] = fy;
+            lt[0][tid] = ft;
+            lu[0][tid] = fu;
+            lg[0][tid] = fg;
         }
         __syncthreads();
-    }
 
-    const int64_t stride = a.rows_pad;
-    double *out = a.partials + chunk * 6 * stride;
+        for (int k = k0; k < k1; ++k) {
+            const int buf = (k - k0) & 1;
+            const bool more = (k + 1 < k1);
+            double px = 0, py = 0, pt = 0, pu = 0;
+            int pg = 0;
+            if (more)
+                fetch((k + 1) * TS + tid, px, py, pt, pu, pg);
+
+            const double first = a.tile[3 * k + 0], last = a.tile[3 * k + 1];
+            const int cls = (last < t_lo) ? CAUSAL : ((first > t_hi) ? ANTI : MIXED);
+            const bool cols = k < k_strict;  // strictly earlier block (so CAUSAL, whole tile)
+
+            // background and triggering terms of source m for the lane's targets
+            auto pair = [&](int m, bool use_bg_all, double &c0, double &c1, double &c2) {
+                const double xm = lx[buf][m], ym = ly[buf][m], tm = lt[buf][m], um = lu[buf][m];
+                const int gm = lg[buf][m];
 #pragma unroll
-    for (int q = 0; q < KT; ++q) {
-        const int64_t i = i0 + tid + q * WG;
-        if (i >= iend)
-            continue;
-        const int64_t rr = i - a.row_begin;
-        out[0 * stride + rr] = acc[q][0];
-        out[3 * stride + rr] = acc[q][3];
-        if (GRAD) {
-            out[1 * stride + rr] = acc[q][1];
-            out[2 * stride + rr] = acc[q][2];
-            out[4 * stride + rr] = acc[q][4];
-            out[5 * stride + rr] = acc[q][5];
+                for (int q = 0; q < KT; ++q) {
+                    const double dx = xn[q] - xm, dy = yn[q] - ym;
+                    const double d2 = dx * dx + dy * dy;
+                    const double dt = tn[q] - tm;
+                    const bool use_b = use_bg_all || (gm != gn[q]);
+                    const bool use_g = (cls == CAUSAL) || (cls == MIXED && gm < gn[q]);
+                    if (use_b) {
+                        const double bb = exp(-(a.ax * d2 + a.at * dt * dt));
+                        acc[q][0] += bb;
+                        c0 += bb;
+                        if (GRAD) {
+                            acc[q][1] += bb * d2;
+                            acc[q][2] += bb * dt * dt;
+                            c1 += bb * d2;
+                            c2 += bb * dt * dt;
+                        }
+                    }
+                    if (use_g) {
+                        const double e = um * exp(-(um * a.qh * d2 + a.omega * dt));
+                        acc[q][3] += e;
+                        if (GRAD) {
+                            acc[q][4] += e * (um * d2);
+                            acc[q][5] += e * dt;
+                        }
+                    }
+                }
+            };
+
+            if (cols) {
+                // 16-lane rotation: lane i takes source m0 + ((i + j) mod 16) at step j
+                for (int m0 = 0; m0 < TS; m0 += 16) {
+                    double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+                    for (int j = 0; j < 16; ++j) {
+                        double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+                        pair(m0 + ((li + j) & 15), true, c0, c1, c2);
+                        e0 = row_rotate_f64(e0) + c0;
+                        if (GRAD) {
+                            e1 = row_rotate_f64(e1) + c1;
+                            e2 = row_rotate_f64(e2) + c2;
+                        }
+                    }
+                    // lane i of each row holds the row's sums of source m0 + ((i + 15) mod 16)
+                    e0 = sum_rows_f64(e0);
+                    if (GRAD) {
+                        e1 = sum_rows_f64(e1);
+                        e2 = sum_rows_f64(e2);
+                    }
+                    if (lane < 16) {
+                        const int mc = m0 + ((li + 15) & 15);
+                        lcol[0][wave][mc] = e0;
+                        if (GRAD) {
+                            lcol[1][wave][mc] = e1;
+                            lcol[2][wave][mc] = e2;
+                        }
+                    }
+                }
+            } else {
+                const int mlen = (k * TS + TS <= a.n) ? TS : a.n - k * TS;
+                for (int m = 0; m < mlen; ++m) {
+                    double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+                    pair(m, cls != MIXED, c0, c1, c2);  // column sums unused
+                }
+            }
+
+            if (more) {
+                const int nb = buf ^ 1;
+                lx[nb][tid] = px;
+                ly[nb][tid] = py;
+                lt[nb][tid] = pt;
+                lu[nb][tid] = pu;
+                lg[nb][tid] = pg;
+            }
+            __syncthreads();
+            if (cols) {
+                // owner lane of source tid: the four waves' sums in a fixed order
+                const int j = k * TS + tid;
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    s0 += lcol[0][w][tid];
+                    if (GRAD) {
+                        s1 += lcol[1][w][tid];
+                        s2 += lcol[2][w][tid];
+                    }
+                }
+                pc[j] += s0;
+                if (GRAD) {
+                    pc[stride + j] += s1;
+                    pc[2 * stride + j] += s2;
+                }
+                __syncthreads();  // lcol is written again by the next tile's columns
+            }
+        }
+
+        double *out = a.prow + int64_t(gc) * 6 * stride;
+#pragma unroll
+        for (int q = 0; q < KT; ++q) {
+            const int i = i0 + tid + q * WG;
+            if (i >= iend)
+                continue;
+            const int rr = i - a.row_begin;
+            out[0 * stride + rr] = acc[q][0];
+            out[3 * stride + rr] = acc[q][3];
+            if (GRAD) {
+                out[1 * stride + rr] = acc[q][1];
+                out[2 * stride + rr] = acc[q][2];
+                out[4 * stride + rr] = acc[q][4];
+                out[5 * stride + rr] = acc[q][5];
+            }
         }
     }
 }
@@ -1530,10 +1630,25 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
     const double tau_x = th->tau_x, tau_t = th->tau_t, h0 = th->h0, omega = th->omega;
     const bool uniform = ev->area > 0.0;
     double *partials = at<double>(ws, L.partials);
-    unsigned pair_blocks = unsigned(P.num_tb * P.num_chunks);
     // the symmetric sweep covers the whole event set; a row range takes the row sweep
-    const bool sym = is_fp32(precision) && g_sym_groups > 0 && rb == 0 && re == n;
+    const bool sym = g_sym_groups > 0 && rb == 0 && re == n;
     const SymPlan SP = sym ? make_sym_plan(P.num_tb, L.num_tiles, g_sym_groups) : SymPlan{};
+    int *sblk = at<int>(ws, L.sblk), *eblk = at<int>(ws, L.eblk);
+    if (sym) {
+        hipLaunchKernelGGL(k_sym_bounds, dim3(unsigned(ceil_div(P.num_tb, 256))), dim3(256), 0, stream, ev->t, n,
+                           P.num_tb, sblk, eblk);
+        if ((rc = check_launch("sym_bounds")) != HAWKES_OK)
+            return rc;
+        hipLaunchKernelGGL(k_sym_plan, dim3(1), dim3(256), 0, stream, eblk, P.num_tb, L.num_tiles, SP.rr, SP.ct,
+                           SP.num_gr, SP.num_gc, at<int>(ws, L.gchi), at<int>(ws, L.g0));
+        if ((rc = check_launch("sym_plan")) != HAWKES_OK)
+            return rc;
+    }
+    // row groups x column groups of the sweep: the symmetric plan, or target blocks x source chunks
+    const int grid_rr = sym ? SP.rr : 1, grid_ct = sym ? SP.ct : int(P.chunk_tiles);
+    const int grid_gr = sym ? SP.num_gr : int(P.num_tb), grid_gc = sym ? SP.num_gc : int(P.num_chunks);
+    const unsigned pair_blocks = unsigned(int64_t(grid_gr) * grid_gc);
+    double *pcol = partials + int64_t(SP.num_gc) * 6 * P.rows_pad;
 
     if (is_fp32(precision)) {
         StageF32 sc;
@@ -1562,40 +1677,20 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
         a.dg = dg;
         a.g = g;
         a.tile = tile;
-        a.sblk = at<int>(ws, L.sblk);
-        a.eblk = at<int>(ws, L.eblk);
+        a.sblk = sblk;
+        a.eblk = eblk;
         a.prow = partials;
         a.row_begin = int(rb);
         a.row_end = int(re);
         a.rows_pad = int(P.rows_pad);
         a.num_tiles = int(L.num_tiles);
         a.num_tb = int(P.num_tb);
-        if (sym) {
-            const SymPlan &S = SP;
-            a.rr = S.rr;
-            a.ct = S.ct;
-            a.num_gr = S.num_gr;
-            a.num_gc = S.num_gc;
-            a.pcol = partials + int64_t(S.num_gc) * 6 * P.rows_pad;
-            a.sym = 1;
-            hipLaunchKernelGGL(k_sym_bounds, dim3(unsigned(ceil_div(P.num_tb, 256))), dim3(256), 0, stream, ev->t,
-                               n, P.num_tb, at<int>(ws, L.sblk), at<int>(ws, L.eblk));
-            if ((rc = check_launch("sym_bounds")) != HAWKES_OK)
-                return rc;
-            hipLaunchKernelGGL(k_sym_plan, dim3(1), dim3(256), 0, stream, at<int>(ws, L.eblk), P.num_tb,
-                               L.num_tiles, S.rr, S.ct, S.num_gr, S.num_gc, at<int>(ws, L.gchi),
-                               at<int>(ws, L.g0));
-            if ((rc = check_launch("sym_plan")) != HAWKES_OK)
-                return rc;
-        } else {
-            a.rr = 1;
-            a.ct = int(P.chunk_tiles);
-            a.num_gr = int(P.num_tb);
-            a.num_gc = int(P.num_chunks);
-            a.pcol = partials;  // unused
-            a.sym = 0;
-        }
-        pair_blocks = unsigned(int64_t(a.num_gr) * a.num_gc);
+        a.rr = grid_rr;
+        a.ct = grid_ct;
+        a.num_gr = grid_gr;
+        a.num_gc = grid_gc;
+        a.pcol = pcol;
+        a.sym = sym ? 1 : 0;
         a.omega = omega;
         a.inv_st = 1.0 / sc.st;
         a.out_s1 = uniform ? 0.0 : 1.0 / (sc.sx * sc.sx);  // D = d^2 sx^2
@@ -1642,15 +1737,21 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
         a.s = ev->s;
         a.g = g;
         a.tile = tile;
-        a.partials = partials;
-        a.n = n;
-        a.row_begin = rb;
-        a.row_end = re;
-        a.rows_pad = P.rows_pad;
-        a.num_tiles = L.num_tiles;
-        a.chunk_tiles = P.chunk_tiles;
-        a.num_chunks = P.num_chunks;
-        a.num_tb = P.num_tb;
+        a.sblk = sblk;
+        a.eblk = eblk;
+        a.prow = partials;
+        a.pcol = pcol;
+        a.n = int(n);
+        a.row_begin = int(rb);
+        a.row_end = int(re);
+        a.rows_pad = int(P.rows_pad);
+        a.num_tiles = int(L.num_tiles);
+        a.num_tb = int(P.num_tb);
+        a.rr = grid_rr;
+        a.ct = grid_ct;
+        a.num_gr = grid_gr;
+        a.num_gc = grid_gc;
+        a.sym = sym ? 1 : 0;
         a.ax = uniform ? 0.0 : 1.0 / (2.0 * tau_x * tau_x);  // uniform background: no spatial factor
         a.at = 1.0 / (2.0 * tau_t * tau_t);
         a.qh = 1.0 / (2.0 * h0 * h0);
@@ -1692,9 +1793,9 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
     f.rr = SP.rr;
     f.ct = SP.ct;
     f.num_gr = SP.num_gr;
-    f.pcol = partials + int64_t(SP.num_gc) * 6 * P.rows_pad;
-    f.gchi = is_fp32(precision) ? at<int>(ws, L.gchi) : nullptr;
-    f.g0 = is_fp32(precision) ? at<int>(ws, L.g0) : nullptr;
+    f.pcol = pcol;
+    f.gchi = at<int>(ws, L.gchi);
+    f.g0 = at<int>(ws, L.g0);
     f.mu = th->mu;
     f.tau_x = tau_x;
     f.tau_t = tau_t;

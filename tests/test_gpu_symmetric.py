@@ -137,3 +137,19 @@ def test_uniform_background_ties_against_row_sweep():
     # fast; the two sweeps agree to a few 1e-10 (measured 2.3e-10), both within 1e-9 of the oracle
     assert sym[0] == pytest.approx(row[0], rel=5e-10)
     np.testing.assert_allclose(sym[2], row[2], rtol=1e-6)
+
+
+@pytest.mark.parametrize("kind", ["dense", "days"])
+def test_fp64_symmetric_against_row_sweep_and_oracle(kind):
+    """The FP64 sweep takes the same symmetric decomposition (column sums in FP64)."""
+    t, ev = _events(kind, 6000, 21)
+    th = synth.theta_default()
+    ll_ref, g_ref, lam_ref, _, _ = oracle.loglik(t, ev.x, ev.y, ev.s, th, per_row=True)
+    dev = hk.DeviceEvents.from_arrays(t, ev.x, ev.y, ev.s)
+    sym = _run(dev, th, "fp64")
+    row = _run(dev, th, "fp64", groups=0)
+    assert abs(sym[0] - ll_ref) <= 1e-12 * abs(ll_ref)
+    np.testing.assert_allclose(sym[1], g_ref, rtol=1e-10)
+    np.testing.assert_allclose(sym[2], lam_ref, rtol=1e-12)
+    assert sym[0] == pytest.approx(row[0], rel=1e-13)
+    np.testing.assert_allclose(sym[1], row[1], rtol=1e-11)
