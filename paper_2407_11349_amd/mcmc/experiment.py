@@ -91,14 +91,34 @@ def find_mode(target, z0, max_iter: int = 200) -> np.ndarray:
     return np.asarray(res.x, dtype=np.float64)
 
 
+# Extra starts of the mode search, as offsets of log theta from z0: the two kernels can trade
+# roles (a long-memory, wide triggering kernel with a narrow background, or the reverse),
+# and the mode nearest to the usual starting values need not be the highest.
+MODE_START_OFFSETS = ([0.0, 0.0, 0.0, -0.5, 0.0, -4.0], [0.0, 0.0, 0.0, -0.8, 1.0, -5.0])
+
+
+def best_mode(target, z0, offsets=MODE_START_OFFSETS, log=None) -> np.ndarray:
+    """The highest of the modes found from z0 and from z0 + each offset."""
+    best, best_lp = None, -np.inf
+    for off in ([0.0] * len(z0),) + tuple(offsets):
+        zm = find_mode(target, np.asarray(z0, dtype=np.float64) + np.asarray(off))
+        lp = target.logp(zm)
+        if log:
+            log(f"mode from offset {off}: z {np.round(zm, 4)} logp {lp:.3f}")
+        if lp > best_lp:
+            best, best_lp = zm, lp
+    return best
+
+
 def burn_in(target: HawkesCutTarget, z0, n_iter: int, n_leapfrog=20, seed=0, n_warmup=300, log=None):
-    """Exact HMC on the cut posterior in three phases: a mode search from z0; n_warmup
-    iterations that tune the step size (dual averaging) and a diagonal mass (variance of the
-    second quarter of the warm-up draws); then n_iter iterations with both fixed, in which
-    every gradient evaluation's tuple is recorded (n_iter (n_leapfrog + 1) tuples)."""
+    """Exact HMC on the cut posterior in three phases: a mode search (the highest mode from
+    several starts); n_warmup iterations that tune the step size (dual averaging) and a
+    diagonal mass (variance of the second quarter of the warm-up draws); then n_iter
+    iterations with both fixed, in which every gradient evaluation's tuple is recorded
+    (n_iter (n_leapfrog + 1) tuples)."""
     t0 = time.time()
     target.resample(0)
-    z = find_mode(target, z0)
+    z = best_mode(target, z0, log=log)
     if log:
         log(f"mode search: z {np.round(z, 4)}")
     hmc = HMC(target, n_leapfrog=n_leapfrog, step_size=0.01, inv_mass=np.full(len(z), 1e-4),
@@ -153,7 +173,7 @@ def run_plain_hmc(target: HawkesCutTarget, hmc: HMC, z0, n_iter: int, it0: int, 
         target.resample(it0 + it + 1)
         s = hmc.init_state(s.z)
         if log and (it + 1) % 200 == 0:
-            log(f"hmc {it + 1}/{n_iter}: accept {acc / (it + 1):.2f}")
+            log(f"hmc {it + 1}/{n_iter}: accept {acc / (it + 1):.2f} z {np.round(s.z, 4)}")
     _sync()
     return ChainResult(np.array(draws), time.time() - t0, target.n_loglik - n0, target.n_grad - g0,
                        {"accept": acc / n_iter})

@@ -17,9 +17,9 @@ seeded recipe with the same shape:
   normalised by its median).
 
 A second recipe, ``generate_clustered``, adds the temporal and space-time
-clustering that the model describes (epidemic waves, and cases that follow
-earlier nearby cases), so that a posterior over the six parameters is
-concentrated; the sampler comparison runs on it.
+clustering that the model describes (epidemic waves with their own hot spots,
+and cases that follow earlier nearby cases), so that a posterior over the six
+parameters is concentrated; the sampler comparison runs on it.
 
 Nothing here evaluates the likelihood.
 """
@@ -126,18 +126,21 @@ def generate(k: str | WorkloadConfig, n: int | None = None, seed: int | None = N
 def generate_clustered(n: int = 100_000, seed: int = 1101, t_max: float = 1000.0, nx: int = 50, ny: int = 60,
                        rho_sdlog: float = 1.0, branching: float = 0.6, delay_days: float = 5.0, h_km: float = 2.0,
                        n_waves: int = 6, wave_sd_days: float = 25.0, uniform_share: float = 0.3) -> EventSet:
-    """A seeded branching (cluster) process with the workloads' spatial layout.
+    """A seeded branching (cluster) process over the workloads' box and county grid.
 
     Immigrant cases: times from ``n_waves`` Gaussian epidemic waves (centres uniform on
-    [0.1, 0.9] t_max, sd ``wave_sd_days``) plus a ``uniform_share`` of uniform times;
-    locations from the 10-centre mixture.  Every case has Poisson(``branching``) offspring,
-    each ``Exp(mean delay_days)`` later and displaced by N(0, (h_km s)^2) per axis, s the
+    [0.1, 0.9] t_max, sd ``wave_sd_days``), each wave with its own 10-centre mixture of
+    locations (centres uniform in the box, sd 20 km), plus a ``uniform_share`` of cases
+    uniform in time and in the box.  Spatial clustering is thus local in time: with one
+    mixture for all times, the long-run persistence of the centres is explained best by a
+    triggering kernel that never decays (omega -> 0), and the posterior runs off along
+    that ridge.  Every case has Poisson(``branching``) offspring, each
+    ``Exp(mean delay_days)`` later and displaced by N(0, (h_km s)^2) per axis, s the
     bandwidth scale of the parent's county.  Cases after t_max are dropped and the set is
     thinned uniformly at random to exactly n events.
     """
     cfg = WorkloadConfig(f"n{n // 1000}k_clustered_{int(t_max)}d_{nx * ny}c", n, t_max, nx, ny, rho_sdlog, seed)
     rng = np.random.default_rng(seed)
-    centres = rng.uniform(0.0, cfg.box_km, (cfg.n_centres, 2))
     rho_county = rng.lognormal(cfg.rho_meanlog, cfg.rho_sdlog, nx * ny)
     wx, wy = cfg.box_km / nx, cfg.box_km / ny
 
@@ -148,12 +151,16 @@ def generate_clustered(n: int = 100_000, seed: int = 1101, t_max: float = 1000.0
 
     n0 = int(1.1 * n * (1.0 - branching))
     n_unif = int(uniform_share * n0)
+    n_wave = n0 - n_unif
     wave_c = rng.uniform(0.1 * t_max, 0.9 * t_max, n_waves)
-    t0 = np.concatenate([rng.uniform(0.0, t_max, n_unif),
-                         wave_c[rng.integers(0, n_waves, n0 - n_unif)] + rng.normal(0.0, wave_sd_days, n0 - n_unif)])
+    wave_centres = rng.uniform(0.0, cfg.box_km, (n_waves, cfg.n_centres, 2))
+    w = rng.integers(0, n_waves, n_wave)
+    t0 = np.concatenate([rng.uniform(0.0, t_max, n_unif), wave_c[w] + rng.normal(0.0, wave_sd_days, n_wave)])
+    xy0 = np.concatenate([rng.uniform(0.0, cfg.box_km, (n_unif, 2)),
+                          wave_centres[w, rng.integers(0, cfg.n_centres, n_wave)]
+                          + rng.normal(0.0, cfg.centre_sd_km, (n_wave, 2))])
     keep = (t0 > 0.0) & (t0 < t_max)
-    t0 = t0[keep]
-    xy0 = centres[rng.integers(0, cfg.n_centres, t0.shape[0])] + rng.normal(0.0, cfg.centre_sd_km, (t0.shape[0], 2))
+    t0, xy0 = t0[keep], xy0[keep]
     med = np.median(rho_county[county_of(xy0)])
     ts, xys = [t0], [xy0]
     gt, gxy = t0, xy0
