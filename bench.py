@@ -255,6 +255,22 @@ def main():
                                   "note": "forward-only sweep (S0, G0 per target), pair kernel time"}
     log(f"fp32 loglik-only pair kernel: {kms_fwd:.1f} ms")
 
+    # two parameter vectors in one forward-only sweep (the pair geometry formed once for both): the
+    # delayed-acceptance correction compares the current and the proposed vector under one draw
+    th2 = np.stack([th, th * np.array([1.02, 0.98, 1.03, 0.97, 1.02, 0.98])])
+    out2 = torch.empty(2, dtype=torch.float64, device="cuda")
+    hk.loglik_batch(dev, th2, precision="fp32", ws=ws, out=out2)
+    hk.set_timing(True)
+    hk.loglik_batch(dev, th2, precision="fp32", ws=ws, out=out2)
+    kms_b2 = hk.last_pair_kernel_ms()
+    hk.set_timing(False)
+    torch.cuda.synchronize()
+    result["fp32_loglik_batch2"] = {
+        "kernel_ms": kms_b2, "cost_vs_one_vector": kms_b2 / kms_fwd,
+        "pairs_per_s": 2 * pairs / (kms_b2 / 1e3),
+        "note": "forward-only sweep for two parameter vectors at once; pairs counted once per vector"}
+    log(f"fp32 loglik batch of 2 pair kernel: {kms_b2:.1f} ms ({kms_b2 / kms_fwd:.2f} x one vector)")
+
     if not args.no_skip:
         # the FP32 sweep without the background terms that are exactly zero in FP32 (time gap
         # past ~14.9 tau_t): same result, less work; reported apart from the O(N^2) metric

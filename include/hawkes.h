@@ -131,6 +131,23 @@ int hawkes_event_terms(const hawkes_events *events, const hawkes_theta *theta, i
                        int64_t row_begin, int64_t row_end, void *ws, size_t ws_bytes,
                        double *d_lambda, double *d_comp, void *stream);
 
+/* Log-likelihoods of rows [row_begin, row_end) for num_theta parameter vectors
+ * on the same events: d_loglik[k] = the hawkes_loglik value at thetas[k]
+ * (thetas: HOST array of num_theta structs; d_loglik: device array of
+ * num_theta doubles).  The parameter kernels of the paper's sampler
+ * (Section 2.3.2) and of delayed acceptance compare the likelihood at two
+ * parameter vectors under the same latent locations.  FP32 and FP32_SKIP
+ * evaluate vectors two at a time in one pair sweep that forms each pair's
+ * differences and squared distance once for both (a vector left over takes
+ * the single sweep); every value meets the same accuracy as hawkes_loglik but
+ * need not equal it bitwise.  FP64 evaluates one vector per sweep.  Every
+ * vector is checked as in hawkes_loglik before any work is enqueued;
+ * num_theta < 1 or a NULL thetas: HAWKES_EINVAL.  The workspace is the one of
+ * hawkes_workspace_bytes(n, precision). */
+int hawkes_loglik_batch(const hawkes_events *events, const hawkes_theta *thetas, int64_t num_theta,
+                        int precision, int64_t row_begin, int64_t row_end, void *ws, size_t ws_bytes,
+                        double *d_loglik, void *stream);
+
 /* The X-update of the cut posterior (paper Section 2.2: latent locations drawn
  * from p(X | coarsened data) in O(N), uniformly within each event's county),
  * with counties as axis-aligned rectangles.

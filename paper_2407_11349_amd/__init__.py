@@ -6,9 +6,9 @@ include/hawkes.h (libhawkes.so); this package is the thin Python binding.
 """
 
 from .likelihood import (DeviceEvents, HawkesLoglik, Workspace, event_terms, hawkes_loglik, last_pair_kernel_ms,
-                         loglik, loglik_grad, resample_locations, set_timing, workspace_bytes)
+                         loglik, loglik_batch, loglik_grad, resample_locations, set_timing, workspace_bytes)
 
 __all__ = [
     "DeviceEvents", "HawkesLoglik", "Workspace", "event_terms", "hawkes_loglik", "last_pair_kernel_ms", "loglik",
-    "loglik_grad", "resample_locations", "set_timing", "workspace_bytes",
+    "loglik_batch", "loglik_grad", "resample_locations", "set_timing", "workspace_bytes",
 ]

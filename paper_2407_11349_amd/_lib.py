@@ -28,7 +28,7 @@ HAWKES_EDATA = -6
 # every entry point declared in include/hawkes.h
 EXPORTS = (
     "hawkes_workspace_bytes", "hawkes_loglik", "hawkes_loglik_grad", "hawkes_event_terms",
-    "hawkes_resample_locations", "hawkes_workspace_status", "hawkes_set_timing",
+    "hawkes_loglik_batch", "hawkes_resample_locations", "hawkes_workspace_status", "hawkes_set_timing",
     "hawkes_last_pair_kernel_ms", "hawkes_tune_target_workgroups", "hawkes_tune_symmetric_groups",
     "hawkes_strerror", "hawkes_last_error",
     # include/hawkes_mlp.h
@@ -73,6 +73,7 @@ def load(path: Path | str | None = None) -> ctypes.CDLL:
     lib.hawkes_loglik.argtypes = common + [vp, vp]
     lib.hawkes_loglik_grad.argtypes = common + [vp, vp, vp]
     lib.hawkes_event_terms.argtypes = common + [vp, vp, vp]
+    lib.hawkes_loglik_batch.argtypes = [ev_p, th_p, i64, ctypes.c_int, i64, i64, vp, ctypes.c_size_t, vp, vp]
     lib.hawkes_resample_locations.argtypes = [i64, vp, vp, i32, u64, u64, vp, vp, vp]
     lib.hawkes_workspace_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int), vp]
     lib.hawkes_set_timing.argtypes = [ctypes.c_int]
@@ -93,7 +94,8 @@ def load(path: Path | str | None = None) -> ctypes.CDLL:
     lib.hawkes_strerror.restype = ctypes.c_char_p
     lib.hawkes_last_error.argtypes = []
     lib.hawkes_last_error.restype = ctypes.c_char_p
-    for name in ("hawkes_loglik", "hawkes_loglik_grad", "hawkes_event_terms", "hawkes_resample_locations",
+    for name in ("hawkes_loglik", "hawkes_loglik_grad", "hawkes_event_terms", "hawkes_loglik_batch",
+                 "hawkes_resample_locations",
                  "hawkes_workspace_status", "hawkes_set_timing", "hawkes_last_pair_kernel_ms",
                  "hawkes_tune_target_workgroups", "hawkes_tune_symmetric_groups", "hawkes_mlp_load",
                  "hawkes_mlp_store", "hawkes_mlp_forward", "hawkes_mlp_loss_grad", "hawkes_mlp_adam_step"):
@@ -128,6 +130,17 @@ def theta_struct(theta) -> Theta:
     if len(vals) != 6:
         raise ValueError("theta must have 6 components (mu, tau_x, tau_t, xi, h0, omega)")
     return Theta(*vals)
+
+
+def theta_array(thetas):
+    """A ctypes array of Theta structs from a (K, 6) array-like of parameter vectors."""
+    rows = thetas.detach().to("cpu", torch.float64).tolist() if isinstance(thetas, torch.Tensor) else list(thetas)
+    if len(rows) < 1:
+        raise ValueError("need at least one parameter vector")
+    arr = (Theta * len(rows))()
+    for k, row in enumerate(rows):
+        arr[k] = theta_struct(row)
+    return arr
 
 
 def ptr(t: torch.Tensor | None) -> int | None:

@@ -39,6 +39,10 @@
 // tiles.  Partial sums go to per-source-range slots that the finalize adds
 // in a fixed order, so results are bitwise reproducible.
 //
+// Several parameter vectors (hawkes_loglik_batch): k_pair_f32_batch sweeps the
+// forward sums of two vectors at once, forming each pair's differences and
+// squared distance once; each vector then takes its own finalize and reduction.
+//
 // Skip mode (HAWKES_FP32_SKIP): the same FP32 sweep without the pairs whose
 // background term is exactly zero in FP32 because the time gap alone puts its
 // exponent past the subnormal range; same results, less work on long spans.
@@ -94,6 +98,7 @@ constexpr int TB = WG * KT;               // target rows per workgroup
 constexpr int GS = HAWKES_GS;             // FP32 terms summed before folding into FP64
 constexpr int64_t MAX_TARGET_WGS = 65536; // upper bound used for workspace sizing
 constexpr int MAX_SYM_GROUPS = 160;       // row / column groups of the symmetric sweep (workspace bound)
+constexpr int MAX_FUSED_THETA = 2;        // parameter vectors one batched sweep evaluates together
 constexpr int64_t MAX_N = int64_t(1) << 30;
 constexpr double LOG2E = 1.4426950408889634074;
 constexpr float LN2F = 0.69314718055994530942f;
@@ -206,8 +211,9 @@ Layout make_layout(int64_t n, int precision)
         L.xs = take(sizeof(double) * L.n_pad);
         L.ys = take(sizeof(double) * L.n_pad);
         L.tsd = take(sizeof(double) * L.n_pad);
-        L.r2 = take(sizeof(float2) * L.n_pad);
-        L.v2 = take(sizeof(float2) * L.n_pad);
+        // r_m and v_m of each vector a batched sweep evaluates (the single sweep uses the first)
+        L.r2 = take(sizeof(float2) * L.n_pad * MAX_FUSED_THETA);
+        L.v2 = take(sizeof(float2) * L.n_pad * MAX_FUSED_THETA);
         L.u2 = take(sizeof(float2) * L.n_pad);
         L.dg = take(sizeof(DeltaGroup) * L.n_pad);
     }
@@ -384,6 +390,34 @@ __global__ __launch_bounds__(256) void k_stage_f32(const double *__restrict__ t,
     u2[i] = make_float2(hi, lo);
     dg[i] = DeltaGroup{float(d), g[i]};
 }
+
+// r_m and v_m (hi, lo) of a further parameter vector for the batched sweep,
+// from the same formulas as k_stage_f32 (rr and omega are that vector's, the
+// position scale inside rr the first vector's).
+__global__ __launch_bounds__(256) void k_stage_f32_rv(const double *__restrict__ t, const double *__restrict__ s,
+                                                      int64_t n, int64_t n_pad, double rr, double omega,
+                                                      const double *__restrict__ tile, float2 *__restrict__ r2,
+                                                      float2 *__restrict__ v2)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n_pad)
+        return;
+    if (i >= n) {
+        r2[i] = v2[i] = make_float2(0.0f, 0.0f);
+        return;
+    }
+    const double tlast = tile[3 * (i / TS) + 1];
+    const double si = s[i];
+    const double u = 1.0 / (si * si);
+    float hi, lo;
+    split_f32(u * rr, hi, lo);
+    r2[i] = make_float2(hi, lo);
+    split_f32(u * exp(-omega * (tlast - t[i])), hi, lo);
+    v2[i] = make_float2(hi, lo);
+}
+
+// Restarts the rescue list (status[1]) before a further vector's finalize.
+__global__ void k_clear_rescue(int *status) { status[1] = 0; }
 
 struct PairF32 {
     const double *xs, *ys, *tsd, *t;
@@ -983,6 +1017,408 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
                 out[2 * stride + rr] = (acc[q][2] - acc[q][1]) * (a.out_s2 * ce);
                 out[4 * stride + rr] = acc[q][4] * (a.out_g1 * ce);
                 out[5 * stride + rr] = acc[q][5] * ce;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------ several theta in one sweep
+//
+// The forward-only FP32 sweep for NT parameter vectors at once (S0 and G0 of
+// each), on the same events and the same work decomposition as k_pair_f32.
+// What the vectors share is computed once per pair: the pair differences and
+// the squared distance in FP64, its FP32 rounding D (the triggering exponent
+// is r_m D with a per-theta r_m) and, for the background of vectors after the
+// first, the squared time difference.  Positions and times are scaled for
+// theta 0; for theta k the background exponent is
+//   A_k = d2 cx_k + dt^2 ct_k  (cx_k = (sx_k / sx_0)^2, ct_k = (st_k / st_0)^2),
+// formed in FP64 and rounded once, as for theta 0.  Per-theta source fields:
+// r_m and v_m (hi, lo); u_m, the time offsets and tie groups are shared.
+// Theta k's row sums go to row-partial slots k (S0) and 3 + k (G0) and its
+// column sums to column slot k, so its finalize reads the same layout as a
+// single forward-only sweep, offset by k slots.
+
+struct PairBatchF32 {
+    const double *xs, *ys, *tsd, *t;  // positions and times scaled for theta 0
+    const float2 *r2, *v2;            // theta k's (hi, lo) fields at r2 + k * theta_stride
+    const float2 *u2;                 // (hi, lo) of u_m
+    const DeltaGroup *dg;
+    const int *g;
+    const double *tile;
+    const int *sblk, *eblk;
+    double *prow, *pcol;
+    int row_begin, row_end, rows_pad, num_tiles, num_tb;
+    int rr, ct, num_gr, num_gc;
+    int sym, window, trig_cull;
+    int theta_stride;
+    const unsigned long long *umax;
+    double skip_gap;   // the largest over the vectors: tiles that early have no background term
+    double omega_min;  // the smallest omega: the latest triggering cut-off
+    double cx[MAX_FUSED_THETA], ct2[MAX_FUSED_THETA], omega[MAX_FUSED_THETA], w2[MAX_FUSED_THETA];
+    double out_exp;
+};
+
+template <int NT, bool UNI>
+__global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32_batch(PairBatchF32 a)
+{
+    static_assert(NT >= 1 && NT <= MAX_FUSED_THETA, "fused theta count");
+    struct TileRecs {
+        double x[TS], y[TS], t[TS];
+        float2 r[NT][TS], v[NT][TS], u[TS];
+        DeltaGroup dg[TS];
+    };
+    __shared__ TileRecs lt2[2];
+    __shared__ float lcol[2][NT][NW][TS];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15;
+    const int gr = a.num_gr - 1 - int(blockIdx.x / unsigned(a.num_gc));
+    const int gc = int(blockIdx.x % unsigned(a.num_gc));
+    const int b_first = gr * a.rr;
+    const int b_stop = (b_first + a.rr < a.num_tb) ? b_first + a.rr : a.num_tb;
+    const int kg0 = gc * a.ct;
+    const int kg1 = (kg0 + a.ct < a.num_tiles) ? kg0 + a.ct : a.num_tiles;
+    const int64_t stride = a.rows_pad;
+    double *pc = a.pcol + int64_t(gr) * 3 * stride;
+    if (a.sym) {
+        const int kend = KT * a.eblk[b_stop - 1];
+        if (kg0 >= (kend < a.num_tiles ? kend : a.num_tiles))
+            return;
+        for (int k = kg0; k < kg1; ++k)
+#pragma unroll
+            for (int z = 0; z < NT; ++z)
+                pc[z * stride + k * TS + tid] = 0.0;
+    }
+
+    auto stage = [&](int k, int buf) {
+        TileRecs &T = lt2[buf];
+        int o = tid;
+        asm volatile("" : "+v"(o));
+        const int wb = tid & ~63;
+        auto copy = [&](const void *src, void *dst) {
+            const unsigned *s = reinterpret_cast<const unsigned *>(src);
+            unsigned *d = reinterpret_cast<unsigned *>(dst);
+            lds_dma4(s + o, d + wb);
+            lds_dma4(s + TS + o, d + TS + wb);
+        };
+        copy(a.xs + k * TS, T.x);
+        copy(a.ys + k * TS, T.y);
+        copy(a.tsd + k * TS, T.t);
+#pragma unroll
+        for (int z = 0; z < NT; ++z) {
+            copy(a.r2 + int64_t(z) * a.theta_stride + k * TS, T.r[z]);
+            copy(a.v2 + int64_t(z) * a.theta_stride + k * TS, T.v[z]);
+        }
+        copy(a.u2 + k * TS, T.u);
+        copy(a.dg + k * TS, T.dg);
+    };
+
+    double cull_gap = a.skip_gap;
+    if (a.trig_cull) {
+        const double um = __longlong_as_double((long long)*a.umax);
+        const double tg = (log(um) + TRIG_SKIP_EXPONENT * LN2) / a.omega_min;
+        cull_gap = (tg > cull_gap) ? tg : cull_gap;
+    }
+
+    for (int b = b_first; b < b_stop; ++b) {
+        const int i0 = a.row_begin + b * TB;
+        const int iend = (i0 + TB < a.row_end) ? i0 + TB : a.row_end;
+        const double t_lo = a.t[i0], t_hi = a.t[iend - 1];
+
+        double xn[KT], yn[KT], tsn[KT], trn[KT];
+        int gn[KT];
+#pragma unroll
+        for (int q = 0; q < KT; ++q) {
+            const int i = i0 + tid + q * WG;
+            const bool in = i < iend;
+            xn[q] = in ? a.xs[i] : PAD_COORD;
+            yn[q] = in ? a.ys[i] : PAD_COORD;
+            tsn[q] = in ? a.tsd[i] : PAD_TIME;
+            trn[q] = a.t[in ? i : iend - 1];
+            gn[q] = in ? a.g[i] : INT_MAX;
+        }
+        double acc[KT][NT][2];
+#pragma unroll
+        for (int q = 0; q < KT; ++q)
+#pragma unroll
+            for (int z = 0; z < NT; ++z)
+                acc[q][z][0] = acc[q][z][1] = 0.0;
+
+        int k_strict = 0, k_end = a.num_tiles, k_lo = 0;
+        if (a.trig_cull) {
+            const double limit = t_lo - cull_gap;
+            int lo = 0, hi = a.num_tiles;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (a.tile[3 * mid + 1] < limit)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            k_lo = lo;
+        }
+        if (a.sym) {
+            k_strict = KT * a.sblk[b];
+            const int e = KT * a.eblk[b];
+            k_end = (e < a.num_tiles) ? e : a.num_tiles;
+        } else if (a.window) {
+            const double limit = t_hi + a.skip_gap;
+            int lo = 0, hi = a.num_tiles;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (a.tile[3 * mid + 0] > limit)
+                    hi = mid;
+                else
+                    lo = mid + 1;
+            }
+            k_end = lo;
+        }
+        const int k0 = (kg0 > k_lo) ? kg0 : k_lo;
+        const int k1 = (kg1 < k_end) ? kg1 : k_end;
+
+        if (k0 < k1)
+            stage(k0, 0);
+        stage_wait();
+        __syncthreads();
+
+        for (int k = k0; k < k1; ++k) {
+            const int buf = (k - k0) & 1;
+            if (k + 1 < k1)
+                stage(k + 1, buf ^ 1);
+
+            const double first = a.tile[3 * k + 0], last = a.tile[3 * k + 1];
+            const int cls = (last < t_lo) ? CAUSAL : ((first > t_hi) ? ANTI : MIXED);
+            const bool trig_only = (cls == CAUSAL) && (t_lo - last > a.skip_gap);
+            const bool cols = (k < k_strict) && !trig_only;
+
+            double gt[KT][NT];
+#pragma unroll
+            for (int q = 0; q < KT; ++q)
+#pragma unroll
+                for (int z = 0; z < NT; ++z)
+                    gt[q][z] = 0.0;
+
+            const TileRecs &T = lt2[buf];
+
+            // background exponents of the NT vectors for one pair (and the shared D)
+            auto bg_terms = [&](double xn_, double yn_, double tn_, double xm, double ym, double tm, float &D,
+                                float (&bz)[NT]) {
+                const double dx = xn_ - xm, dy = yn_ - ym, dt = tn_ - tm;
+                const double d2 = fma(dy, dy, dx * dx);
+                D = float(d2);
+                const double dt2 = dt * dt;
+#pragma unroll
+                for (int z = 0; z < NT; ++z) {
+                    if (UNI) {
+                        const double a2 = (z == 0) ? dt2 : dt2 * a.ct2[z];
+                        const float A = float(a2), Alo = float(a2 - double(A));
+                        const float e = __builtin_amdgcn_exp2f(-A);
+                        bz[z] = fmaf(-LN2F * Alo, e, e);
+                    } else {
+                        const float A = (z == 0) ? float(fma(dt, dt, d2)) : float(fma(dt2, a.ct2[z], d2 * a.cx[z]));
+                        bz[z] = __builtin_amdgcn_exp2f(-A);
+                    }
+                }
+            };
+
+            if (cls != MIXED) {
+                const bool causal = (cls == CAUSAL);
+                float e[NT];
+                double h[NT];
+#pragma unroll
+                for (int z = 0; z < NT; ++z) {
+                    e[z] = 0.0f;
+                    h[z] = 0.0;
+                }
+                for (int m0 = 0; m0 < TS; m0 += GS) {
+                    float f[KT][NT][2];
+#pragma unroll
+                    for (int q = 0; q < KT; ++q)
+#pragma unroll
+                        for (int z = 0; z < NT; ++z)
+                            f[q][z][0] = f[q][z][1] = 0.0f;
+                    // background + triggering terms of source m for the lane's targets;
+                    // adds each vector's background terms over those targets to c[z]
+                    auto causal_pair = [&](int m, float (&c)[NT]) {
+                        const double xm = T.x[m], ym = T.y[m], tm = T.t[m];
+#pragma unroll
+                        for (int q = 0; q < KT; ++q) {
+                            float D, bz[NT];
+                            bg_terms(xn[q], yn[q], tsn[q], xm, ym, tm, D, bz);
+#pragma unroll
+                            for (int z = 0; z < NT; ++z) {
+                                const float2 rm = T.r[z][m], vm = T.v[z][m];
+                                const float t1 = fmaf(rm.y, D, rm.x * D);
+                                const float E = __builtin_amdgcn_exp2f(-t1);
+                                const float p = fmaf(vm.y, E, vm.x * E);
+                                f[q][z][0] += bz[z];
+                                f[q][z][1] += p;
+                                c[z] += bz[z];
+                            }
+                        }
+                    };
+                    auto trig_pair = [&](int m) {
+                        const double xm = T.x[m], ym = T.y[m];
+#pragma unroll
+                        for (int q = 0; q < KT; ++q) {
+                            const float D = geom_d(xn[q], yn[q], xm, ym);
+#pragma unroll
+                            for (int z = 0; z < NT; ++z) {
+                                const float2 rm = T.r[z][m], vm = T.v[z][m];
+                                const float t1 = fmaf(rm.y, D, rm.x * D);
+                                const float E = __builtin_amdgcn_exp2f(-t1);
+                                f[q][z][1] += fmaf(vm.y, E, vm.x * E);
+                            }
+                        }
+                    };
+                    const int sub = m0 & ~15, s0 = m0 & 15;
+                    if (trig_only) {
+                        HK_UNROLL(HAWKES_UJ)
+                        for (int j = 0; j < GS; ++j)
+                            trig_pair(m0 + j);
+                    } else if (cols) {
+                        HK_UNROLL(HAWKES_UJ)
+                        for (int j = 0; j < GS; ++j) {
+                            float c[NT];
+#pragma unroll
+                            for (int z = 0; z < NT; ++z)
+                                c[z] = 0.0f;
+                            causal_pair(sub + ((li + s0 + j) & 15), c);
+#pragma unroll
+                            for (int z = 0; z < NT; ++z)
+                                e[z] = row_rotate_f32(e[z]) + c[z];
+                        }
+                        if (s0 == 0) {
+#pragma unroll
+                            for (int z = 0; z < NT; ++z)
+                                h[z] = double(e[z]);
+                        } else {
+                            double w[NT];
+#pragma unroll
+                            for (int z = 0; z < NT; ++z)
+                                w[z] = sum_rows_f64(row_shift8_f64(h[z]) + double(e[z]));
+                            if (lane < 16) {
+                                const int mc = sub + ((li + 15) & 15);
+#pragma unroll
+                                for (int z = 0; z < NT; ++z)
+                                    lcol[buf][z][wave][mc] = float(w[z]);
+                            }
+                        }
+#pragma unroll
+                        for (int z = 0; z < NT; ++z)
+                            e[z] = 0.0f;
+                    } else if (causal) {
+                        HK_UNROLL(HAWKES_UJ)
+                        for (int j = 0; j < GS; ++j) {
+                            float c[NT];
+#pragma unroll
+                            for (int z = 0; z < NT; ++z)
+                                c[z] = 0.0f;
+                            causal_pair(m0 + j, c);  // column sums unused
+                        }
+                    } else {
+                        HK_UNROLL(HAWKES_UJ)
+                        for (int j = 0; j < GS; ++j) {
+                            const int m = m0 + j;
+                            const double xm = T.x[m], ym = T.y[m], tm = T.t[m];
+#pragma unroll
+                            for (int q = 0; q < KT; ++q) {
+                                float D, bz[NT];
+                                bg_terms(xn[q], yn[q], tsn[q], xm, ym, tm, D, bz);
+#pragma unroll
+                                for (int z = 0; z < NT; ++z)
+                                    f[q][z][0] += bz[z];
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < KT; ++q)
+#pragma unroll
+                        for (int z = 0; z < NT; ++z) {
+                            if (!trig_only)
+                                acc[q][z][0] += double(f[q][z][0]);
+                            if (causal)
+                                gt[q][z] += double(f[q][z][1]);
+                        }
+                }
+                if (causal) {
+#pragma unroll
+                    for (int q = 0; q < KT; ++q) {
+                        const double dn = trn[q] - last;
+#pragma unroll
+                        for (int z = 0; z < NT; ++z)
+                            acc[q][z][1] += exp(-a.omega[z] * dn) * gt[q][z];
+                    }
+                }
+            } else {
+                // tiles overlapping the block's time range: tie-group masks and the
+                // triggering time factor per pair in FP64
+                for (int m0 = 0; m0 < TS; m0 += GS) {
+                    float f[KT][NT][2];
+#pragma unroll
+                    for (int q = 0; q < KT; ++q)
+#pragma unroll
+                        for (int z = 0; z < NT; ++z)
+                            f[q][z][0] = f[q][z][1] = 0.0f;
+                    for (int j = 0; j < GS; ++j) {
+                        const int m = m0 + j;
+                        const double xm = T.x[m], ym = T.y[m], tm = T.t[m];
+                        const float2 um = T.u[m];
+                        const int gm = T.dg[m].g;
+#pragma unroll
+                        for (int q = 0; q < KT; ++q) {
+                            float D, bz[NT];
+                            bg_terms(xn[q], yn[q], tsn[q], xm, ym, tm, D, bz);
+                            const double dt = tsn[q] - tm;
+#pragma unroll
+                            for (int z = 0; z < NT; ++z) {
+                                const float2 rm = T.r[z][m];
+                                const float b = (gm != gn[q]) ? bz[z] : 0.0f;
+                                const float t1 = fmaf(rm.y, D, rm.x * D);
+                                const float arg = float(fma(a.w2[z], dt, double(t1)));
+                                const float E = __builtin_amdgcn_exp2f(-arg);
+                                const float p = fmaf(um.y, E, um.x * E);
+                                f[q][z][0] += b;
+                                f[q][z][1] += (gm < gn[q]) ? p : 0.0f;
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < KT; ++q)
+#pragma unroll
+                        for (int z = 0; z < NT; ++z) {
+                            acc[q][z][0] += double(f[q][z][0]);
+                            acc[q][z][1] += double(f[q][z][1]);
+                        }
+                }
+            }
+
+            stage_wait();
+            __syncthreads();
+
+            if (cols) {
+                const int j = k * TS + tid;
+#pragma unroll
+                for (int z = 0; z < NT; ++z) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int w = 0; w < NW; ++w)
+                        s += double(lcol[buf][z][w][tid]);
+                    pc[z * stride + j] += s * a.out_exp;
+                }
+            }
+        }
+
+        double *out = a.prow + int64_t(gc) * 6 * stride;
+#pragma unroll
+        for (int q = 0; q < KT; ++q) {
+            const int i = i0 + tid + q * WG;
+            if (i >= iend)
+                continue;
+            const int rr = i - a.row_begin;
+#pragma unroll
+            for (int z = 0; z < NT; ++z) {
+                out[z * stride + rr] = acc[q][z][0] * a.out_exp;
+                out[(3 + z) * stride + rr] = acc[q][z][1] * a.out_exp;
             }
         }
     }
@@ -1590,6 +2026,197 @@ T *at(void *ws, size_t off)
 
 enum Mode { MODE_LOGLIK, MODE_GRAD, MODE_TERMS };
 
+// What every call stages before its pair sweep: tie groups, tile time ranges
+// and data checks; the work plan; for the symmetric sweep its block bounds.
+struct Setup {
+    Plan P;
+    SymPlan SP;
+    bool sym = false, uniform = false;
+    int grid_rr = 1, grid_ct = 1, grid_gr = 0, grid_gc = 0;
+    unsigned pair_blocks = 0, stage_blocks = 0;
+    int64_t n = 0, rb = 0, re = 0, rows = 0;
+    int *status = nullptr, *g = nullptr, *sblk = nullptr, *eblk = nullptr;
+    double *tile = nullptr, *partials = nullptr, *pcol = nullptr;
+};
+
+int setup(const hawkes_events *ev, int64_t rb, int64_t re, void *ws, const Layout &L, hipStream_t stream,
+          Setup &S)
+{
+    int rc;
+    S.n = ev->n;
+    S.rb = rb;
+    S.re = re;
+    S.rows = re - rb;
+    S.uniform = ev->area > 0.0;
+    S.status = at<int>(ws, L.status);
+    S.g = at<int>(ws, L.g);
+    S.tile = at<double>(ws, L.tile);
+    S.sblk = at<int>(ws, L.sblk);
+    S.eblk = at<int>(ws, L.eblk);
+    S.partials = at<double>(ws, L.partials);
+
+    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, stream, S.status);
+    S.stage_blocks = unsigned(ceil_div(L.n_pad, 256));
+    hipLaunchKernelGGL(k_stage_common, dim3(S.stage_blocks), dim3(256), 0, stream, ev->t, ev->x, ev->y, ev->s, S.n,
+                       L.n_pad, S.g, S.tile, S.status);
+    if ((rc = check_launch("stage_common")) != HAWKES_OK || S.rows == 0)
+        return rc;
+
+    S.P = make_plan(S.rows, L.num_tiles);
+    // the symmetric sweep covers the whole event set; a row range takes the row sweep
+    S.sym = g_sym_groups > 0 && rb == 0 && re == S.n;
+    S.SP = S.sym ? make_sym_plan(S.P.num_tb, L.num_tiles, g_sym_groups) : SymPlan{};
+    if (S.sym) {
+        hipLaunchKernelGGL(k_sym_bounds, dim3(unsigned(ceil_div(S.P.num_tb, 256))), dim3(256), 0, stream, ev->t,
+                           S.n, S.P.num_tb, S.sblk, S.eblk);
+        if ((rc = check_launch("sym_bounds")) != HAWKES_OK)
+            return rc;
+        hipLaunchKernelGGL(k_sym_plan, dim3(1), dim3(256), 0, stream, S.eblk, S.P.num_tb, L.num_tiles, S.SP.rr,
+                           S.SP.ct, S.SP.num_gr, S.SP.num_gc, at<int>(ws, L.gchi), at<int>(ws, L.g0));
+        if ((rc = check_launch("sym_plan")) != HAWKES_OK)
+            return rc;
+    }
+    // row groups x column groups of the sweep: the symmetric plan, or target blocks x source chunks
+    S.grid_rr = S.sym ? S.SP.rr : 1;
+    S.grid_ct = S.sym ? S.SP.ct : int(S.P.chunk_tiles);
+    S.grid_gr = S.sym ? S.SP.num_gr : int(S.P.num_tb);
+    S.grid_gc = S.sym ? S.SP.num_gc : int(S.P.num_chunks);
+    S.pair_blocks = unsigned(int64_t(S.grid_gr) * S.grid_gc);
+    S.pcol = S.partials + int64_t(S.SP.num_gc) * 6 * S.P.rows_pad;
+    return HAWKES_OK;
+}
+
+// FP32 source staging scales: positions by the background's spatial scale
+// (or by the triggering bandwidth h0 when the background is spatially
+// uniform), times by the temporal one.
+StageF32 stage_scales(const hawkes_theta *th, bool uniform)
+{
+    StageF32 sc;
+    const double tau_sp = uniform ? th->h0 : th->tau_x;
+    sc.sx = std::sqrt(LOG2E / (2.0 * tau_sp * tau_sp));
+    sc.st = std::sqrt(LOG2E / (2.0 * th->tau_t * th->tau_t));
+    sc.rr = (tau_sp / th->h0) * (tau_sp / th->h0);
+    sc.omega = th->omega;
+    return sc;
+}
+
+// The sweep's grid and partial-sum fields shared by the FP32 kernels.
+template <typename A>
+void fill_grid(A &a, const Setup &S, const Layout &L)
+{
+    a.tile = S.tile;
+    a.sblk = S.sblk;
+    a.eblk = S.eblk;
+    a.prow = S.partials;
+    a.pcol = S.pcol;
+    a.row_begin = int(S.rb);
+    a.row_end = int(S.re);
+    a.rows_pad = int(S.P.rows_pad);
+    a.num_tiles = int(L.num_tiles);
+    a.num_tb = int(S.P.num_tb);
+    a.rr = S.grid_rr;
+    a.ct = S.grid_ct;
+    a.num_gr = S.grid_gr;
+    a.num_gc = S.grid_gc;
+    a.sym = S.sym ? 1 : 0;
+}
+
+Fin make_fin(const hawkes_events *ev, const hawkes_theta *th, int precision, const Setup &S, const Layout &L,
+             void *ws, double *d_lam, double *d_comp)
+{
+    const double tau_x = th->tau_x, tau_t = th->tau_t, h0 = th->h0, omega = th->omega;
+    Fin f;
+    f.t = ev->t;
+    f.x = ev->x;
+    f.y = ev->y;
+    f.s = ev->s;
+    f.g = S.g;
+    f.partials = S.partials;
+    f.status = S.status;
+    f.rescue = at<int>(ws, L.rescue);
+    f.rowvals = at<double>(ws, L.rowvals);
+    f.lam_out = d_lam;
+    f.comp_out = d_comp;
+    f.n = S.n;
+    f.row_begin = S.rb;
+    f.rows = S.rows;
+    f.rows_pad = S.P.rows_pad;
+    f.rows_cap = L.rows_cap;
+    f.num_chunks = S.P.num_chunks;
+    f.sym = S.sym ? 1 : 0;
+    f.rr = S.SP.rr;
+    f.ct = S.SP.ct;
+    f.num_gr = S.SP.num_gr;
+    f.pcol = S.pcol;
+    f.gchi = at<int>(ws, L.gchi);
+    f.g0 = at<int>(ws, L.g0);
+    f.mu = th->mu;
+    f.tau_x = tau_x;
+    f.tau_t = tau_t;
+    f.xi = th->xi;
+    f.h0 = h0;
+    f.omega = omega;
+    f.uniform = S.uniform ? 1 : 0;
+    f.c_b = S.uniform ? 1.0 / (ev->area * std::sqrt(2.0 * M_PI) * tau_t)
+                      : 1.0 / (std::pow(2.0 * M_PI, 1.5) * tau_x * tau_x * tau_t);
+    f.c_g = omega / (2.0 * M_PI * h0 * h0);
+    f.ax = S.uniform ? 0.0 : 1.0 / (2.0 * tau_x * tau_x);
+    f.at = 1.0 / (2.0 * tau_t * tau_t);
+    f.qh = 1.0 / (2.0 * h0 * h0);
+    // Each FP32 pair term below 2^-126 may be lost to underflow; n of them
+    // bound the loss by n 2^-126 (mu c_b + xi c_g).  Rows whose rate is not
+    // 1/RESCUE_REL times larger than that are recomputed in FP64.
+    f.rescue_lambda = is_fp32(precision)
+                          ? double(S.n) * std::ldexp(1.0, -126) * (f.mu * f.c_b + f.xi * f.c_g) / RESCUE_REL
+                          : 0.0;
+    return f;
+}
+
+// After the pair sweep: per-row finalize, FP64 rescue (FP32), and either the
+// per-row outputs or the fixed-order reduction.
+int finish(const Fin &f, const Setup &S, const Layout &L, void *ws, int precision, Mode mode, double *d_loglik,
+           double *d_grad, double *d_lam, double *d_comp, hipStream_t stream)
+{
+    int rc;
+    const bool grad = (mode == MODE_GRAD);
+    const int64_t nblk = ceil_div(S.rows, 256);
+    if (grad)
+        hipLaunchKernelGGL(k_finalize<true>, dim3(unsigned(nblk)), dim3(256), 0, stream, f);
+    else
+        hipLaunchKernelGGL(k_finalize<false>, dim3(unsigned(nblk)), dim3(256), 0, stream, f);
+    if ((rc = check_launch("finalize")) != HAWKES_OK)
+        return rc;
+    if (is_fp32(precision)) {
+        const unsigned rescue_wgs = unsigned(nblk < 256 ? nblk : 256);
+        if (grad)
+            hipLaunchKernelGGL(k_rescue<true>, dim3(rescue_wgs), dim3(256), 0, stream, f);
+        else
+            hipLaunchKernelGGL(k_rescue<false>, dim3(rescue_wgs), dim3(256), 0, stream, f);
+        if ((rc = check_launch("rescue")) != HAWKES_OK)
+            return rc;
+    }
+    if (mode == MODE_TERMS) {
+        hipLaunchKernelGGL(k_poison_rows, dim3(unsigned(nblk)), dim3(256), 0, stream, S.status, d_lam, d_comp,
+                           S.rows);
+        return check_launch("poison_rows");
+    }
+    double *blocks = at<double>(ws, L.blocks);
+    if (grad)
+        hipLaunchKernelGGL(k_blocksum<true>, dim3(unsigned(nblk)), dim3(256), 0, stream, f.rowvals, S.rows,
+                           L.rows_cap, blocks);
+    else
+        hipLaunchKernelGGL(k_blocksum<false>, dim3(unsigned(nblk)), dim3(256), 0, stream, f.rowvals, S.rows,
+                           L.rows_cap, blocks);
+    if ((rc = check_launch("blocksum")) != HAWKES_OK)
+        return rc;
+    if (grad)
+        hipLaunchKernelGGL(k_reduce<true>, dim3(1), dim3(256), 0, stream, blocks, nblk, S.status, d_loglik, d_grad);
+    else
+        hipLaunchKernelGGL(k_reduce<false>, dim3(1), dim3(256), 0, stream, blocks, nblk, S.status, d_loglik,
+                           nullptr);
+    return check_launch("reduce");
+}
+
 int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t rb, int64_t re, void *ws,
         size_t ws_bytes, double *d_loglik, double *d_grad, double *d_lam, double *d_comp, Mode mode, void *stream_)
 {
@@ -1607,66 +2234,28 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
     }
     hipStream_t stream = as_stream(stream_);
     const bool grad = (mode == MODE_GRAD);
-    const int64_t n = ev->n;
-    int *status = at<int>(ws, L.status);
-    int *g = at<int>(ws, L.g);
-    double *tile = at<double>(ws, L.tile);
-
-    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, stream, status);
-    const unsigned stage_blocks = unsigned(ceil_div(L.n_pad, 256));
-    hipLaunchKernelGGL(k_stage_common, dim3(stage_blocks), dim3(256), 0, stream, ev->t, ev->x, ev->y, ev->s, n,
-                       L.n_pad, g, tile, status);
-    if ((rc = check_launch("stage_common")) != HAWKES_OK)
+    Setup S;
+    if ((rc = setup(ev, rb, re, ws, L, stream, S)) != HAWKES_OK)
         return rc;
-
-    const int64_t rows = re - rb;
-    if (rows == 0) {
+    if (S.rows == 0) {
         if (mode != MODE_TERMS)
             hipLaunchKernelGGL(k_zero_outputs, dim3(1), dim3(64), 0, stream, d_loglik, grad ? d_grad : nullptr);
         return check_launch("zero_outputs");
     }
-
-    const Plan P = make_plan(rows, L.num_tiles);
-    const double tau_x = th->tau_x, tau_t = th->tau_t, h0 = th->h0, omega = th->omega;
-    const bool uniform = ev->area > 0.0;
-    double *partials = at<double>(ws, L.partials);
-    // the symmetric sweep covers the whole event set; a row range takes the row sweep
-    const bool sym = g_sym_groups > 0 && rb == 0 && re == n;
-    const SymPlan SP = sym ? make_sym_plan(P.num_tb, L.num_tiles, g_sym_groups) : SymPlan{};
-    int *sblk = at<int>(ws, L.sblk), *eblk = at<int>(ws, L.eblk);
-    if (sym) {
-        hipLaunchKernelGGL(k_sym_bounds, dim3(unsigned(ceil_div(P.num_tb, 256))), dim3(256), 0, stream, ev->t, n,
-                           P.num_tb, sblk, eblk);
-        if ((rc = check_launch("sym_bounds")) != HAWKES_OK)
-            return rc;
-        hipLaunchKernelGGL(k_sym_plan, dim3(1), dim3(256), 0, stream, eblk, P.num_tb, L.num_tiles, SP.rr, SP.ct,
-                           SP.num_gr, SP.num_gc, at<int>(ws, L.gchi), at<int>(ws, L.g0));
-        if ((rc = check_launch("sym_plan")) != HAWKES_OK)
-            return rc;
-    }
-    // row groups x column groups of the sweep: the symmetric plan, or target blocks x source chunks
-    const int grid_rr = sym ? SP.rr : 1, grid_ct = sym ? SP.ct : int(P.chunk_tiles);
-    const int grid_gr = sym ? SP.num_gr : int(P.num_tb), grid_gc = sym ? SP.num_gc : int(P.num_chunks);
-    const unsigned pair_blocks = unsigned(int64_t(grid_gr) * grid_gc);
-    double *pcol = partials + int64_t(SP.num_gc) * 6 * P.rows_pad;
+    const double h0 = th->h0, omega = th->omega;
+    const bool uniform = S.uniform;
 
     if (is_fp32(precision)) {
-        StageF32 sc;
-        // positions are scaled by the background's spatial scale, or by the triggering
-        // bandwidth h0 when the background is spatially uniform
-        const double tau_sp = uniform ? h0 : tau_x;
-        sc.sx = std::sqrt(LOG2E / (2.0 * tau_sp * tau_sp));
-        sc.st = std::sqrt(LOG2E / (2.0 * tau_t * tau_t));
-        sc.rr = (tau_sp / h0) * (tau_sp / h0);
-        sc.omega = omega;
+        const StageF32 sc = stage_scales(th, uniform);
         double *xs = at<double>(ws, L.xs), *ys = at<double>(ws, L.ys), *tsd = at<double>(ws, L.tsd);
         float2 *r2 = at<float2>(ws, L.r2), *v2 = at<float2>(ws, L.v2), *u2 = at<float2>(ws, L.u2);
         DeltaGroup *dg = at<DeltaGroup>(ws, L.dg);
-        hipLaunchKernelGGL(k_stage_f32, dim3(stage_blocks), dim3(256), 0, stream, ev->t, ev->x, ev->y, ev->s, g,
-                           n, L.n_pad, sc, tile, xs, ys, tsd, r2, v2, u2, dg);
+        hipLaunchKernelGGL(k_stage_f32, dim3(S.stage_blocks), dim3(256), 0, stream, ev->t, ev->x, ev->y, ev->s,
+                           S.g, S.n, L.n_pad, sc, S.tile, xs, ys, tsd, r2, v2, u2, dg);
         if ((rc = check_launch("stage_f32")) != HAWKES_OK)
             return rc;
         PairF32 a;
+        fill_grid(a, S, L);
         a.xs = xs;
         a.ys = ys;
         a.tsd = tsd;
@@ -1675,22 +2264,7 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
         a.v2 = v2;
         a.u2 = u2;
         a.dg = dg;
-        a.g = g;
-        a.tile = tile;
-        a.sblk = sblk;
-        a.eblk = eblk;
-        a.prow = partials;
-        a.row_begin = int(rb);
-        a.row_end = int(re);
-        a.rows_pad = int(P.rows_pad);
-        a.num_tiles = int(L.num_tiles);
-        a.num_tb = int(P.num_tb);
-        a.rr = grid_rr;
-        a.ct = grid_ct;
-        a.num_gr = grid_gr;
-        a.num_gc = grid_gc;
-        a.pcol = pcol;
-        a.sym = sym ? 1 : 0;
+        a.g = S.g;
         a.omega = omega;
         a.inv_st = 1.0 / sc.st;
         a.out_s1 = uniform ? 0.0 : 1.0 / (sc.sx * sc.sx);  // D = d^2 sx^2
@@ -1698,13 +2272,14 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
         a.out_g1 = 2.0 * h0 * h0 / LOG2E;        // t1 = u d^2 log2(e) / (2 h0^2)
         a.w2 = omega * LOG2E / sc.st;
         a.out_exp = 1.0 / (1.0 + EXP2_MEAN_REL_ERR);
-        a.umax = reinterpret_cast<const unsigned long long *>(status) + STATUS_UMAX;
+        a.umax = reinterpret_cast<const unsigned long long *>(S.status) + STATUS_UMAX;
         if (precision == HAWKES_FP32_SKIP) {
             // scaled time gap whose square exceeds 160: exp2(-A) <= 2^-160 is 0 in FP32
             a.skip_gap = std::sqrt(SKIP_EXPONENT) / sc.st;
             a.window = 1;
             a.trig_cull = 1;
-            hipLaunchKernelGGL(k_umax, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, stream, ev->s, n, status);
+            hipLaunchKernelGGL(k_umax, dim3(unsigned(ceil_div(S.n, 256))), dim3(256), 0, stream, ev->s, S.n,
+                               S.status);
             if ((rc = check_launch("umax")) != HAWKES_OK)
                 return rc;
         } else {
@@ -1714,14 +2289,15 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
         }
         if (g_timing && (rc = record_event(g_ev_start, stream)) != HAWKES_OK)
             return rc;
+        const dim3 grid(S.pair_blocks);
         if (grad && uniform)
-            hipLaunchKernelGGL((k_pair_f32<true, true>), dim3(pair_blocks), dim3(WG), 0, stream, a);
+            hipLaunchKernelGGL((k_pair_f32<true, true>), grid, dim3(WG), 0, stream, a);
         else if (grad)
-            hipLaunchKernelGGL((k_pair_f32<true, false>), dim3(pair_blocks), dim3(WG), 0, stream, a);
+            hipLaunchKernelGGL((k_pair_f32<true, false>), grid, dim3(WG), 0, stream, a);
         else if (uniform)
-            hipLaunchKernelGGL((k_pair_f32<false, true>), dim3(pair_blocks), dim3(WG), 0, stream, a);
+            hipLaunchKernelGGL((k_pair_f32<false, true>), grid, dim3(WG), 0, stream, a);
         else
-            hipLaunchKernelGGL((k_pair_f32<false, false>), dim3(pair_blocks), dim3(WG), 0, stream, a);
+            hipLaunchKernelGGL((k_pair_f32<false, false>), grid, dim3(WG), 0, stream, a);
         if (g_timing) {
             if ((rc = record_event(g_ev_stop, stream)) != HAWKES_OK)
                 return rc;
@@ -1735,33 +2311,33 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
         a.x = ev->x;
         a.y = ev->y;
         a.s = ev->s;
-        a.g = g;
-        a.tile = tile;
-        a.sblk = sblk;
-        a.eblk = eblk;
-        a.prow = partials;
-        a.pcol = pcol;
-        a.n = int(n);
+        a.g = S.g;
+        a.tile = S.tile;
+        a.sblk = S.sblk;
+        a.eblk = S.eblk;
+        a.prow = S.partials;
+        a.pcol = S.pcol;
+        a.n = int(S.n);
         a.row_begin = int(rb);
         a.row_end = int(re);
-        a.rows_pad = int(P.rows_pad);
+        a.rows_pad = int(S.P.rows_pad);
         a.num_tiles = int(L.num_tiles);
-        a.num_tb = int(P.num_tb);
-        a.rr = grid_rr;
-        a.ct = grid_ct;
-        a.num_gr = grid_gr;
-        a.num_gc = grid_gc;
-        a.sym = sym ? 1 : 0;
-        a.ax = uniform ? 0.0 : 1.0 / (2.0 * tau_x * tau_x);  // uniform background: no spatial factor
-        a.at = 1.0 / (2.0 * tau_t * tau_t);
+        a.num_tb = int(S.P.num_tb);
+        a.rr = S.grid_rr;
+        a.ct = S.grid_ct;
+        a.num_gr = S.grid_gr;
+        a.num_gc = S.grid_gc;
+        a.sym = S.sym ? 1 : 0;
+        a.ax = uniform ? 0.0 : 1.0 / (2.0 * th->tau_x * th->tau_x);  // uniform background: no spatial factor
+        a.at = 1.0 / (2.0 * th->tau_t * th->tau_t);
         a.qh = 1.0 / (2.0 * h0 * h0);
         a.omega = omega;
         if (g_timing && (rc = record_event(g_ev_start, stream)) != HAWKES_OK)
             return rc;
         if (grad)
-            hipLaunchKernelGGL(k_pair_f64<true>, dim3(pair_blocks), dim3(WG), 0, stream, a);
+            hipLaunchKernelGGL(k_pair_f64<true>, dim3(S.pair_blocks), dim3(WG), 0, stream, a);
         else
-            hipLaunchKernelGGL(k_pair_f64<false>, dim3(pair_blocks), dim3(WG), 0, stream, a);
+            hipLaunchKernelGGL(k_pair_f64<false>, dim3(S.pair_blocks), dim3(WG), 0, stream, a);
         if (g_timing) {
             if ((rc = record_event(g_ev_stop, stream)) != HAWKES_OK)
                 return rc;
@@ -1771,84 +2347,134 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
             return rc;
     }
 
-    Fin f;
-    f.t = ev->t;
-    f.x = ev->x;
-    f.y = ev->y;
-    f.s = ev->s;
-    f.g = g;
-    f.partials = partials;
-    f.status = status;
-    f.rescue = at<int>(ws, L.rescue);
-    f.rowvals = at<double>(ws, L.rowvals);
-    f.lam_out = d_lam;
-    f.comp_out = d_comp;
-    f.n = n;
-    f.row_begin = rb;
-    f.rows = rows;
-    f.rows_pad = P.rows_pad;
-    f.rows_cap = L.rows_cap;
-    f.num_chunks = P.num_chunks;
-    f.sym = sym ? 1 : 0;
-    f.rr = SP.rr;
-    f.ct = SP.ct;
-    f.num_gr = SP.num_gr;
-    f.pcol = pcol;
-    f.gchi = at<int>(ws, L.gchi);
-    f.g0 = at<int>(ws, L.g0);
-    f.mu = th->mu;
-    f.tau_x = tau_x;
-    f.tau_t = tau_t;
-    f.xi = th->xi;
-    f.h0 = h0;
-    f.omega = omega;
-    f.uniform = uniform ? 1 : 0;
-    f.c_b = uniform ? 1.0 / (ev->area * std::sqrt(2.0 * M_PI) * tau_t)
-                    : 1.0 / (std::pow(2.0 * M_PI, 1.5) * tau_x * tau_x * tau_t);
-    f.c_g = omega / (2.0 * M_PI * h0 * h0);
-    f.ax = uniform ? 0.0 : 1.0 / (2.0 * tau_x * tau_x);
-    f.at = 1.0 / (2.0 * tau_t * tau_t);
-    f.qh = 1.0 / (2.0 * h0 * h0);
-    // Each FP32 pair term below 2^-126 may be lost to underflow; n of them
-    // bound the loss by n 2^-126 (mu c_b + xi c_g).  Rows whose rate is not
-    // 1/RESCUE_REL times larger than that are recomputed in FP64.
-    f.rescue_lambda = is_fp32(precision)
-                          ? double(n) * std::ldexp(1.0, -126) * (f.mu * f.c_b + f.xi * f.c_g) / RESCUE_REL
-                          : 0.0;
-    const int64_t nblk = ceil_div(rows, 256);
-    if (grad)
-        hipLaunchKernelGGL(k_finalize<true>, dim3(unsigned(nblk)), dim3(256), 0, stream, f);
-    else
-        hipLaunchKernelGGL(k_finalize<false>, dim3(unsigned(nblk)), dim3(256), 0, stream, f);
-    if ((rc = check_launch("finalize")) != HAWKES_OK)
+    const Fin f = make_fin(ev, th, precision, S, L, ws, d_lam, d_comp);
+    return finish(f, S, L, ws, precision, mode, d_loglik, d_grad, d_lam, d_comp, stream);
+}
+
+// Several parameter vectors on the same events and rows.  FP32: pairs of
+// vectors share one forward-only sweep (k_pair_f32_batch), a vector left over
+// takes the single sweep; FP64: one sweep per vector.
+int run_batch(const hawkes_events *ev, const hawkes_theta *th, int64_t num_theta, int precision, int64_t rb,
+              int64_t re, void *ws, size_t ws_bytes, double *d_loglik, void *stream_)
+{
+    if (!th || num_theta < 1) {
+        set_error("need at least one theta (got %lld, pointer %p)", (long long)num_theta, (const void *)th);
+        return HAWKES_EINVAL;
+    }
+    if (!d_loglik) {
+        set_error("null loglik output");
+        return HAWKES_EINVAL;
+    }
+    Layout L;
+    int rc;
+    for (int64_t k = 0; k < num_theta; ++k)
+        if ((rc = validate(ev, th + k, precision, rb, re, ws, ws_bytes, &L)) != HAWKES_OK)
+            return rc;
+    if (!is_fp32(precision) || num_theta == 1 || re == rb) {
+        for (int64_t k = 0; k < num_theta; ++k)
+            if ((rc = run(ev, th + k, precision, rb, re, ws, ws_bytes, d_loglik + k, nullptr, nullptr, nullptr,
+                          MODE_LOGLIK, stream_)) != HAWKES_OK)
+                return rc;
+        return HAWKES_OK;
+    }
+    hipStream_t stream = as_stream(stream_);
+    Setup S;
+    if ((rc = setup(ev, rb, re, ws, L, stream, S)) != HAWKES_OK)
         return rc;
-    if (is_fp32(precision)) {
-        const unsigned rescue_wgs = unsigned(nblk < 256 ? nblk : 256);
-        if (grad)
-            hipLaunchKernelGGL(k_rescue<true>, dim3(rescue_wgs), dim3(256), 0, stream, f);
-        else
-            hipLaunchKernelGGL(k_rescue<false>, dim3(rescue_wgs), dim3(256), 0, stream, f);
-        if ((rc = check_launch("rescue")) != HAWKES_OK)
+    if (precision == HAWKES_FP32_SKIP) {
+        hipLaunchKernelGGL(k_umax, dim3(unsigned(ceil_div(S.n, 256))), dim3(256), 0, stream, ev->s, S.n, S.status);
+        if ((rc = check_launch("umax")) != HAWKES_OK)
             return rc;
     }
-    if (mode == MODE_TERMS) {
-        hipLaunchKernelGGL(k_poison_rows, dim3(unsigned(nblk)), dim3(256), 0, stream, status, d_lam, d_comp, rows);
-        return check_launch("poison_rows");
+    double *xs = at<double>(ws, L.xs), *ys = at<double>(ws, L.ys), *tsd = at<double>(ws, L.tsd);
+    float2 *r2 = at<float2>(ws, L.r2), *v2 = at<float2>(ws, L.v2), *u2 = at<float2>(ws, L.u2);
+    DeltaGroup *dg = at<DeltaGroup>(ws, L.dg);
+    int64_t k = 0;
+    for (; k + MAX_FUSED_THETA <= num_theta; k += MAX_FUSED_THETA) {
+        const hawkes_theta *t0 = th + k;
+        const StageF32 sc0 = stage_scales(t0, S.uniform);
+        hipLaunchKernelGGL(k_stage_f32, dim3(S.stage_blocks), dim3(256), 0, stream, ev->t, ev->x, ev->y, ev->s,
+                           S.g, S.n, L.n_pad, sc0, S.tile, xs, ys, tsd, r2, v2, u2, dg);
+        if ((rc = check_launch("stage_f32")) != HAWKES_OK)
+            return rc;
+        PairBatchF32 a;
+        fill_grid(a, S, L);
+        a.xs = xs;
+        a.ys = ys;
+        a.tsd = tsd;
+        a.t = ev->t;
+        a.r2 = r2;
+        a.v2 = v2;
+        a.u2 = u2;
+        a.dg = dg;
+        a.g = S.g;
+        a.theta_stride = int(L.n_pad);
+        a.umax = reinterpret_cast<const unsigned long long *>(S.status) + STATUS_UMAX;
+        a.out_exp = 1.0 / (1.0 + EXP2_MEAN_REL_ERR);
+        double max_tau_t = 0.0, min_omega = HUGE_VAL;
+        const double tau_sp0 = S.uniform ? t0->h0 : t0->tau_x;
+        for (int z = 0; z < MAX_FUSED_THETA; ++z) {
+            const hawkes_theta *tz = t0 + z;
+            if (z > 0) {
+                // theta z's r_m and v_m with theta 0's position scale
+                const double rr = (tau_sp0 / tz->h0) * (tau_sp0 / tz->h0);
+                hipLaunchKernelGGL(k_stage_f32_rv, dim3(S.stage_blocks), dim3(256), 0, stream, ev->t, ev->s, S.n,
+                                   L.n_pad, rr, tz->omega, S.tile, r2 + int64_t(z) * L.n_pad,
+                                   v2 + int64_t(z) * L.n_pad);
+                if ((rc = check_launch("stage_f32_rv")) != HAWKES_OK)
+                    return rc;
+            }
+            a.cx[z] = (t0->tau_x / tz->tau_x) * (t0->tau_x / tz->tau_x);
+            a.ct2[z] = (t0->tau_t / tz->tau_t) * (t0->tau_t / tz->tau_t);
+            a.omega[z] = tz->omega;
+            a.w2[z] = tz->omega * LOG2E / sc0.st;
+            max_tau_t = std::fmax(max_tau_t, tz->tau_t);
+            min_omega = std::fmin(min_omega, tz->omega);
+        }
+        a.omega_min = min_omega;
+        if (precision == HAWKES_FP32_SKIP) {
+            // every vector's background term is exactly zero past the largest gap
+            a.skip_gap = std::sqrt(SKIP_EXPONENT) / std::sqrt(LOG2E / (2.0 * max_tau_t * max_tau_t));
+            a.window = 1;
+            a.trig_cull = 1;
+        } else {
+            a.skip_gap = HUGE_VAL;
+            a.window = 0;
+            a.trig_cull = 0;
+        }
+        if (g_timing && (rc = record_event(g_ev_start, stream)) != HAWKES_OK)
+            return rc;
+        if (S.uniform)
+            hipLaunchKernelGGL((k_pair_f32_batch<MAX_FUSED_THETA, true>), dim3(S.pair_blocks), dim3(WG), 0, stream,
+                               a);
+        else
+            hipLaunchKernelGGL((k_pair_f32_batch<MAX_FUSED_THETA, false>), dim3(S.pair_blocks), dim3(WG), 0,
+                               stream, a);
+        if (g_timing) {
+            if ((rc = record_event(g_ev_stop, stream)) != HAWKES_OK)
+                return rc;
+            g_timing_recorded = true;
+        }
+        if ((rc = check_launch("pair_f32_batch")) != HAWKES_OK)
+            return rc;
+        for (int z = 0; z < MAX_FUSED_THETA; ++z) {
+            // vector z's sums sit z slots further on in the row and column partials
+            Fin f = make_fin(ev, t0 + z, precision, S, L, ws, nullptr, nullptr);
+            f.partials = S.partials + int64_t(z) * S.P.rows_pad;
+            f.pcol = S.pcol + int64_t(z) * S.P.rows_pad;
+            hipLaunchKernelGGL(k_clear_rescue, dim3(1), dim3(1), 0, stream, S.status);
+            if ((rc = check_launch("clear_rescue")) != HAWKES_OK)
+                return rc;
+            if ((rc = finish(f, S, L, ws, precision, MODE_LOGLIK, d_loglik + k + z, nullptr, nullptr, nullptr,
+                             stream)) != HAWKES_OK)
+                return rc;
+        }
     }
-    double *blocks = at<double>(ws, L.blocks);
-    if (grad)
-        hipLaunchKernelGGL(k_blocksum<true>, dim3(unsigned(nblk)), dim3(256), 0, stream, f.rowvals, rows, L.rows_cap,
-                           blocks);
-    else
-        hipLaunchKernelGGL(k_blocksum<false>, dim3(unsigned(nblk)), dim3(256), 0, stream, f.rowvals, rows,
-                           L.rows_cap, blocks);
-    if ((rc = check_launch("blocksum")) != HAWKES_OK)
-        return rc;
-    if (grad)
-        hipLaunchKernelGGL(k_reduce<true>, dim3(1), dim3(256), 0, stream, blocks, nblk, status, d_loglik, d_grad);
-    else
-        hipLaunchKernelGGL(k_reduce<false>, dim3(1), dim3(256), 0, stream, blocks, nblk, status, d_loglik, nullptr);
-    return check_launch("reduce");
+    for (; k < num_theta; ++k)
+        if ((rc = run(ev, th + k, precision, rb, re, ws, ws_bytes, d_loglik + k, nullptr, nullptr, nullptr,
+                      MODE_LOGLIK, stream_)) != HAWKES_OK)
+            return rc;
+    return HAWKES_OK;
 }
 
 }  // namespace
@@ -1908,6 +2534,13 @@ extern "C" int hawkes_event_terms(const hawkes_events *events, const hawkes_thet
 {
     return run(events, theta, precision, row_begin, row_end, ws, ws_bytes, nullptr, nullptr, d_lambda, d_comp,
                MODE_TERMS, stream);
+}
+
+extern "C" int hawkes_loglik_batch(const hawkes_events *events, const hawkes_theta *thetas, int64_t num_theta,
+                                   int precision, int64_t row_begin, int64_t row_end, void *ws, size_t ws_bytes,
+                                   double *d_loglik, void *stream)
+{
+    return run_batch(events, thetas, num_theta, precision, row_begin, row_end, ws, ws_bytes, d_loglik, stream);
 }
 
 extern "C" int hawkes_workspace_status(const void *ws, int *status, void *stream)

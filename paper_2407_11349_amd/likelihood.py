@@ -123,6 +123,24 @@ def loglik_grad(events: DeviceEvents, theta, precision="fp32", rows=None, ws=Non
     return out, grad
 
 
+def loglik_batch(events: DeviceEvents, thetas, precision="fp32", rows=None, ws=None, out=None,
+                 stream=None) -> torch.Tensor:
+    """Log-likelihoods of rows [r0, r1) at each of K parameter vectors (a (K, 6) array-like) as a
+    K-element float64 device tensor (asynchronous); FP32 evaluates them two per pair sweep."""
+    lib = _lib.load()
+    w = _workspace(events, precision, ws)
+    r0, r1 = _rows(events, rows)
+    arr = _lib.theta_array(thetas)
+    k = len(arr)
+    out = torch.empty(k, dtype=torch.float64, device=events.t.device) if out is None else out
+    if out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous() or out.numel() < k:
+        raise ValueError("out must be a contiguous float64 CUDA tensor of at least K elements")
+    ev = events.struct()
+    _lib.check(lib.hawkes_loglik_batch(ctypes.byref(ev), arr, k, _lib.precision_code(precision), r0, r1, w.ptr,
+                                       w.nbytes, _lib.ptr(out), _lib.stream_handle(stream)), "hawkes_loglik_batch")
+    return out
+
+
 def event_terms(events: DeviceEvents, theta, precision="fp32", rows=None, ws=None, stream=None):
     """(lambda_n, Lambda_n) for the rows, float64 device tensors."""
     lib = _lib.load()

@@ -28,6 +28,7 @@ class HawkesCutTarget:
         self.ws = lk.Workspace(events.n, precision, events.t.device)
         self.out = torch.empty(1, dtype=torch.float64, device=events.t.device)
         self.grad = torch.empty(6, dtype=torch.float64, device=events.t.device)
+        self.out_batch = None
         self.n_loglik = 0
         self.n_grad = 0
 
@@ -47,6 +48,24 @@ class HawkesCutTarget:
         self.n_loglik += 1
         lp, _ = self._prior(z)
         return float(self.out.item()) + lp
+
+    def logp_batch(self, zs) -> np.ndarray:
+        """log p(z_k | X, t) for several points under the current draw, the likelihoods from one
+        batched call (two parameter vectors per FP32 pair sweep)."""
+        zs = [np.asarray(z, dtype=np.float64) for z in zs]
+        out = np.full(len(zs), -np.inf)
+        ok = [k for k, z in enumerate(zs) if np.all(np.isfinite(z)) and not np.any(np.abs(z) > 50)]
+        if not ok:
+            return out
+        if self.out_batch is None or self.out_batch.numel() < len(ok):
+            self.out_batch = torch.empty(len(ok), dtype=torch.float64, device=self.ev.t.device)
+        th = np.exp(np.stack([zs[k] for k in ok]))
+        lk.loglik_batch(self.ev, th, precision=self.precision, ws=self.ws, out=self.out_batch)
+        vals = self.out_batch[:len(ok)].cpu().numpy()
+        self.n_loglik += len(ok)
+        for j, k in enumerate(ok):
+            out[k] = float(vals[j]) + self._prior(zs[k])[0]
+        return out
 
     def logp_and_grad(self, z):
         z = np.asarray(z, dtype=np.float64)

@@ -9,6 +9,12 @@ leaves the exact posterior invariant whatever the surrogate's error; the
 surrogate only changes how often proposals survive.  When the acceptance rate
 over the last `window` iterations falls below `fallback_below`, iterations are
 exact HMC (exact gradients) until it recovers.
+
+Under the cut posterior the target changes with every latent-location draw, so
+the exact value at the current point is needed afresh each iteration, but only
+when a proposal reaches stage 2.  It is computed then, together with the
+proposal's value in one two-vector evaluation when the target offers
+`logp_batch` (the FP32 sweep forms each pair's geometry once for both).
 """
 
 from __future__ import annotations
@@ -24,7 +30,7 @@ from .hmc import HMC, HMCState, kinetic, leapfrog
 @dataclass
 class DAState:
     z: np.ndarray
-    logp: float          # exact log posterior at z (under the current target)
+    logp: float | None   # exact log posterior at z under the current target (None: not yet computed)
     s: float             # surrogate log posterior at z
     s_grad: np.ndarray   # its gradient
 
@@ -43,7 +49,8 @@ class DelayedAcceptanceHMC:
         self.fallback_below = fallback_below
         self.exact = HMC(target, dim=dim, n_leapfrog=n_leapfrog, step_size=step_size, inv_mass=self.inv_mass,
                          rng=self.rng)
-        self.stats = {"iterations": 0, "stage1_accept": 0, "stage2_accept": 0, "fallback": 0, "accept": 0}
+        self.stats = {"iterations": 0, "stage1_accept": 0, "stage2_accept": 0, "fallback": 0, "accept": 0,
+                      "paired_exact": 0}
 
     def init_state(self, z) -> DAState:
         z = np.asarray(z, dtype=np.float64)
@@ -51,8 +58,18 @@ class DelayedAcceptanceHMC:
         return DAState(z, self.target.logp(z), s, sg)
 
     def refresh_exact(self, st: DAState) -> DAState:
-        """Recompute the exact log posterior at the current point (after the target changed)."""
-        return DAState(st.z, self.target.logp(st.z), st.s, st.s_grad)
+        """The target changed (a new latent-location draw): the exact value at the current point is
+        stale and is recomputed when a stage-2 correction next needs it."""
+        return DAState(st.z, None, st.s, st.s_grad)
+
+    def _exact_pair(self, z0, z1):
+        """Exact log posteriors at the current point and the proposal under the same target."""
+        batch = getattr(self.target, "logp_batch", None)
+        self.stats["paired_exact"] += 1
+        if batch is not None:
+            v = batch([z0, z1])
+            return float(v[0]), float(v[1])
+        return self.target.logp(z0), self.target.logp(z1)
 
     def in_fallback(self) -> bool:
         return len(self.window) == self.window.maxlen and np.mean(self.window) < self.fallback_below
@@ -80,7 +97,11 @@ class DelayedAcceptanceHMC:
             self.window.append(0.0)
             return st, False, "stage1"
         self.stats["stage1_accept"] += 1
-        logp1 = self.target.logp(z1)
+        if st.logp is None:
+            lp0, logp1 = self._exact_pair(st.z, z1)
+            st = DAState(st.z, lp0, st.s, st.s_grad)
+        else:
+            logp1 = self.target.logp(z1)
         log_a2 = (logp1 - s1) - (st.logp - st.s)
         a2 = float(np.exp(min(0.0, log_a2))) if np.isfinite(logp1) else 0.0
         if self.rng.uniform() < a2:

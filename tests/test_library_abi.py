@@ -96,3 +96,32 @@ def test_host_validation_paths(lib):
     assert lib.hawkes_tune_symmetric_groups(-1) == -1
     assert lib.hawkes_tune_symmetric_groups(161) == -1
     assert lib.hawkes_last_pair_kernel_ms(None) == -1
+
+
+def test_batch_host_validation(lib):
+    ev = _ev(1000)
+    ws_need = lib.hawkes_workspace_bytes(1000, 1)
+    fake = 0x200000  # never dereferenced: every call below fails host validation
+    good = (0.5, 10.0, 7.0, 0.3, 2.0, 0.2)
+    arr = (_lib.Theta * 3)(_lib.Theta(*good), _lib.Theta(*good), _lib.Theta(*good))
+    call = lib.hawkes_loglik_batch
+    assert call(ctypes.byref(ev), arr, 0, 1, 0, 10, fake, ws_need, fake, None) == -1
+    assert call(ctypes.byref(ev), None, 2, 1, 0, 10, fake, ws_need, fake, None) == -1
+    assert call(ctypes.byref(ev), arr, 2, 1, 0, 10, fake, ws_need, None, None) == -1
+    assert call(ctypes.byref(ev), arr, 2, 7, 0, 10, fake, ws_need, fake, None) == -1
+    assert call(ctypes.byref(ev), arr, 2, 1, 0, 1001, fake, ws_need, fake, None) == -2
+    assert call(ctypes.byref(ev), arr, 2, 1, 0, 10, fake, ws_need - 256, fake, None) == -3
+    # a bad component in any vector is caught before work is enqueued
+    for k in range(3):
+        vals = list(good)
+        vals[5] = float("nan")
+        bad = (_lib.Theta * 3)(*[_lib.Theta(*(vals if j == k else good)) for j in range(3)])
+        assert call(ctypes.byref(ev), bad, 3, 1, 0, 10, fake, ws_need, fake, None) == -1
+        assert b"theta" in lib.hawkes_last_error()
+    # theta_array marshals (K, 6) inputs and rejects bad shapes
+    a = _lib.theta_array([good, good])
+    assert len(a) == 2 and a[1].omega == 0.2
+    with pytest.raises(ValueError):
+        _lib.theta_array([])
+    with pytest.raises(ValueError):
+        _lib.theta_array([good[:5]])

@@ -150,3 +150,49 @@ def test_univariate_mh_recovers_gaussian_moments_and_adapts():
     assert np.all(np.abs(mh.acceptance() - 0.44) < 0.1)
     _check_moments(draws, mu, C)
     assert lp == pytest.approx(tgt.logp(z))
+
+
+class DrawTarget(Gauss):
+    """A Gaussian whose mean moves with every latent-location draw (as l(theta; X) does), with a
+    batched log density that records how many vectors each call carries."""
+
+    def __init__(self, mu, Q):
+        super().__init__(mu, Q)
+        self.mu0 = self.mu.copy()
+        self.batches = []
+
+    def resample(self, it):
+        self.mu = self.mu0 + 0.05 * np.random.default_rng([7, it]).normal(size=6)
+
+    def logp_batch(self, zs):
+        self.batches.append(len(zs))
+        return np.array([Gauss.logp(self, z) for z in zs])
+
+
+def test_delayed_acceptance_lazy_refresh_pairs_exact_values():
+    """After each draw the current point's exact value is recomputed only when a proposal reaches
+    stage 2, in one two-vector call; the chain equals the one that recomputes it eagerly."""
+    from paper_2407_11349_amd.mcmc.da_hmc import DAState
+
+    _, mu, C = _target(4)
+    chains = []
+    for lazy in (True, False):
+        tgt = DrawTarget(mu, np.linalg.inv(C))
+        sur = Gauss(mu + 0.1, np.linalg.inv(1.2 * C))
+        da = DelayedAcceptanceHMC(tgt, sur.logp_and_grad, n_leapfrog=10, step_size=0.15,
+                                  rng=np.random.default_rng(8), fallback_below=0.0)
+        tgt.resample(0)
+        st = da.init_state(np.zeros(6))
+        zs = []
+        for it in range(400):
+            st, _, _ = da.step(st)
+            zs.append(st.z.copy())
+            tgt.resample(it + 1)
+            st = da.refresh_exact(st) if lazy else DAState(st.z, Gauss.logp(tgt, st.z), st.s, st.s_grad)
+        chains.append(np.array(zs))
+        if lazy:
+            # every stage-2 correction after the first draw change takes the paired call
+            assert da.stats["stage1_accept"] - 1 <= da.stats["paired_exact"] <= da.stats["stage1_accept"]
+            assert da.stats["paired_exact"] > 100
+            assert tgt.batches and set(tgt.batches) == {2}
+    np.testing.assert_allclose(chains[0], chains[1], rtol=0, atol=1e-12)
