@@ -8,8 +8,10 @@ Inputs are synthetic and resident in HBM before timing starts.
 
 Prints one JSON line.  Extra fields: the same evaluation in the FP64 sweep,
 the FP32 skip mode (same result without the exactly-zero background terms;
-reported apart, never as the O(N^2) metric), the roofline of the dominant
-kernel (pair sweep), and the FP64 CPU oracle timed on a bounded sample of
+reported apart, never as the O(N^2) metric), the forward-only sweep for one
+and for two parameter vectors, the roofline of the dominant kernel (pair
+sweep), the path's smaller steps (latent-location draw, surrogate inference
+and training step), and the FP64 CPU oracle timed on a bounded sample of
 target rows on the host cores.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1]
@@ -99,6 +101,91 @@ def cpu_baseline(ev, th, budget_s: float = 15.0) -> dict:
                       f"{dt:.1f} s"}
 
 
+# Surrogate network 6 -> 256 -> 256 -> 256 -> 1: multiply-adds of one pass through its weights (biases and GELUs
+# not counted), and the passes per sample of inference (value + input gradient) and of one training step
+# (primal, input-gradient reverse, tangent along the gradient residual, the reverse of primal and tangent
+# through W3 and W2 (two cotangents each), and the per-sample weight-gradient outer products, two per matrix).
+MLP_H, MLP_DZ = 256, 6
+MLP_MACS = MLP_DZ * MLP_H + 2 * MLP_H * MLP_H + MLP_H
+MLP_INFER_FLOP = 2 * 2 * MLP_MACS
+MLP_TRAIN_FLOP = 2 * (MLP_MACS                      # primal
+                      + MLP_MACS                    # reverse for grad_z f
+                      + MLP_DZ * MLP_H + 2 * MLP_H * MLP_H  # tangent along r
+                      + 4 * MLP_H * MLP_H           # two cotangents through W3^T and W2^T
+                      + 2 * MLP_MACS)               # weight-gradient outer products (two per matrix)
+HBM_PEAK_GBS = 8000.0
+
+
+def event_ms(torch, fn, reps: int) -> float:
+    """Average milliseconds per call of fn, by HIP events on torch's current stream (the library enqueues its
+    kernels there), after one untimed call."""
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def component_timings(hk, torch, county, rect, x, y) -> dict:
+    """The path's smaller steps: the latent-location draw at the workload's size, and the surrogate network's
+    inference (batch 1, as inside a leapfrog trajectory, and a large batch) and training step."""
+    from paper_2407_11349_amd.surrogate import P as MLP_P, SurrogateNet
+    from synth.mlp_init import init_params
+
+    n = int(county.shape[0])
+    it = [0]
+
+    def draw():
+        it[0] += 1
+        hk.resample_locations(county, rect, 2002, it[0], x, y)
+
+    ms = event_ms(torch, draw, 50)
+    nbytes = n * (4 + 16) + rect.numel() * 8  # county id in, x and y out, the rectangle table once
+    out = {"resample": {"us_per_call": ms * 1e3, "events": n, "algorithmic_bytes": nbytes,
+                        "achieved_gbs": nbytes / (ms / 1e3) / 1e9,
+                        "frac_of_hbm_peak": nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}}
+    net = SurrogateNet(init_params(0))
+    g = torch.Generator(device="cuda").manual_seed(0)
+    z1 = torch.randn(1, 6, device="cuda", generator=g)
+    zb = torch.randn(21000, 6, device="cuda", generator=g)
+    ms1 = event_ms(torch, lambda: net.forward(z1), 200)
+    msb = event_ms(torch, lambda: net.forward(zb), 10)
+    t0 = time.perf_counter()
+    for _ in range(50):
+        f, gz = net.forward(z1)
+        f.cpu(), gz.cpu()
+    host_us = (time.perf_counter() - t0) / 50 * 1e6
+    out["mlp_forward"] = {
+        "batch1_us": ms1 * 1e3, "batch1_host_round_trip_us": host_us,
+        "batch21000_ms": msb, "samples_per_s": 21000 / (msb / 1e3),
+        "flop_per_sample": MLP_INFER_FLOP, "achieved_tflops": MLP_INFER_FLOP * 21000 / (msb / 1e3) / 1e12,
+        "frac_of_fp32_peak": MLP_INFER_FLOP * 21000 / (msb / 1e3) / 1e12 / PEAK_FP32_TFLOPS,
+        "note": "value and input gradient; one workgroup per sample, BF16 weights, FP32 accumulation"}
+    B = 256
+    zt = torch.randn(B, 6, device="cuda", generator=g)
+    yt = torch.randn(B, device="cuda", generator=g)
+    gt = torch.randn(B, 6, device="cuda", generator=g)
+    grad = torch.empty(MLP_P, dtype=torch.float32, device="cuda")
+    step = [0]
+
+    def train_step():
+        step[0] += 1
+        net.loss_grad(zt, yt, gt, 1.0, grad=grad)
+        net.adam_step(grad, step[0], 1e-4)
+
+    mst = event_ms(torch, train_step, 50)
+    out["mlp_train_step"] = {
+        "batch": B, "ms_per_step": mst, "flop_per_sample": MLP_TRAIN_FLOP,
+        "achieved_tflops": MLP_TRAIN_FLOP * B / (mst / 1e3) / 1e12,
+        "frac_of_fp32_peak": MLP_TRAIN_FLOP * B / (mst / 1e3) / 1e12 / PEAK_FP32_TFLOPS,
+        "note": "Sobolev loss, parameter gradient and Adam update for one batch"}
+    return out
+
+
 def run_ess(args, hk, synth, torch):
     """ESS/s of delayed-acceptance HMC with the BF16 surrogate against plain exact-gradient HMC, both on the
     cut posterior (X redrawn every iteration) with the FP32 GPU likelihood, 20 leapfrog steps."""
@@ -135,6 +222,8 @@ def main():
     ap.add_argument("--ess-warmup", type=int, default=300)
     ap.add_argument("--ess-burn", type=int, default=1000)
     ap.add_argument("--ess-iter", type=int, default=2000)
+    ap.add_argument("--components", action="store_true",
+                    help="only time the smaller steps (latent-location draw, surrogate inference and training)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES device-to-device (scales the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -168,6 +257,10 @@ def main():
     dev = hk.DeviceEvents.from_arrays(ev.t, ev.x, ev.y, ev.s, device="cuda")
     county = torch.from_numpy(ev.county).cuda()
     rect = torch.from_numpy(ev.rect).cuda()
+    if args.components:
+        print(json.dumps({"workload": cfg.name, "n_events": n,
+                          "components": component_timings(hk, torch, county, rect, dev.x, dev.y)}), flush=True)
+        return
     ws = hk.Workspace(n, "fp32")
     out_ll = torch.empty(1, dtype=torch.float64, device="cuda")
     out_g = torch.empty(6, dtype=torch.float64, device="cuda")
@@ -297,6 +390,12 @@ def main():
             "note": "pairs whose background term is exactly 0 in FP32 are not swept; not the O(N^2) metric"}
         log(f"fp32_skip evaluation: {dskip * 1e3:.1f} ms (kernel {kms_skip:.1f} ms)")
         del wss
+
+    comp = component_timings(hk, torch, county, rect, dev.x, dev.y)
+    result["components"] = comp
+    log(f"resample {comp['resample']['us_per_call']:.1f} us ({comp['resample']['achieved_gbs']:.0f} GB/s); "
+        f"mlp forward batch 1 {comp['mlp_forward']['batch1_us']:.1f} us, batch 21000 "
+        f"{comp['mlp_forward']['batch21000_ms']:.2f} ms; train step {comp['mlp_train_step']['ms_per_step']:.3f} ms")
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
