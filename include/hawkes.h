@@ -138,9 +138,12 @@ int hawkes_event_terms(const hawkes_events *events, const hawkes_theta *theta, i
  * (Section 2.3.2) and of delayed acceptance compare the likelihood at two
  * parameter vectors under the same latent locations.  FP32 and FP32_SKIP
  * evaluate vectors two at a time in one pair sweep that forms each pair's
- * differences and squared distance once for both (a vector left over takes
- * the single sweep); every value meets the same accuracy as hawkes_loglik but
- * need not equal it bitwise.  FP64 evaluates one vector per sweep.  Every
+ * differences once for both (a vector left over takes the single sweep).
+ * Each value equals the hawkes_loglik value at the same vector up to a
+ * last-bit FP32 rounding in a few pairs per billion (10^-15 relative at
+ * n = 10^6; the first vector of each fused pair bitwise in FP32), so it does
+ * not depend on the vector it is paired with (FP32_SKIP: beyond the summation
+ * order of the far triggering tiles).  FP64 evaluates one vector per sweep.  Every
  * vector is checked as in hawkes_loglik before any work is enqueued;
  * num_theta < 1 or a NULL thetas: HAWKES_EINVAL.  The workspace is the one of
  * hawkes_workspace_bytes(n, precision). */

@@ -392,8 +392,7 @@ __global__ __launch_bounds__(256) void k_stage_f32(const double *__restrict__ t,
 }
 
 // r_m and v_m (hi, lo) of a further parameter vector for the batched sweep,
-// from the same formulas as k_stage_f32 (rr and omega are that vector's, the
-// position scale inside rr the first vector's).
+// from the same formulas as k_stage_f32 (rr and omega are that vector's).
 __global__ __launch_bounds__(256) void k_stage_f32_rv(const double *__restrict__ t, const double *__restrict__ s,
                                                       int64_t n, int64_t n_pad, double rr, double omega,
                                                       const double *__restrict__ tile, float2 *__restrict__ r2,
@@ -1027,13 +1026,14 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
 // The forward-only FP32 sweep for NT parameter vectors at once (S0 and G0 of
 // each), on the same events and the same work decomposition as k_pair_f32.
 // What the vectors share is computed once per pair: the pair differences and
-// the squared distance in FP64, its FP32 rounding D (the triggering exponent
-// is r_m D with a per-theta r_m) and, for the background of vectors after the
-// first, the squared time difference.  Positions and times are scaled for
-// theta 0; for theta k the background exponent is
-//   A_k = d2 cx_k + dt^2 ct_k  (cx_k = (sx_k / sx_0)^2, ct_k = (st_k / st_0)^2),
-// formed in FP64 and rounded once, as for theta 0.  Per-theta source fields:
-// r_m and v_m (hi, lo); u_m, the time offsets and tie groups are shared.
+// the squared distance d2 in FP64 and, for vectors after the first, the
+// squared time difference.  Positions and times are scaled for theta 0; for
+// theta k the squared distance in its own scale is d2 cx_k and the background
+// exponent A_k = d2 cx_k + dt^2 ct_k (cx_k = (sx_k / sx_0)^2,
+// ct_k = (st_k / st_0)^2), each formed in FP64 and rounded once to FP32, so
+// that every FP32 value of theta k is the one a single sweep at theta k forms
+// (up to FP64 rounding).  Per-theta source fields: r_m and v_m (hi, lo);
+// u_m, the time offsets and tie groups are shared.
 // Theta k's row sums go to row-partial slots k (S0) and 3 + k (G0) and its
 // column sums to column slot k, so its finalize reads the same layout as a
 // single forward-only sweep, offset by k slots.
@@ -1054,6 +1054,7 @@ struct PairBatchF32 {
     const unsigned long long *umax;
     double skip_gap;   // the largest over the vectors: tiles that early have no background term
     double omega_min;  // the smallest omega: the latest triggering cut-off
+    // (sx_k / sx_0)^2 and (st_k / st_0)^2: theta k's spatial and temporal scales against theta 0's
     double cx[MAX_FUSED_THETA], ct2[MAX_FUSED_THETA], omega[MAX_FUSED_THETA], w2[MAX_FUSED_THETA];
     double out_exp;
 };
@@ -1199,25 +1200,37 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32_batch(PairBatchF32
 
             const TileRecs &T = lt2[buf];
 
-            // background exponents of the NT vectors for one pair (and the shared D)
-            auto bg_terms = [&](double xn_, double yn_, double tn_, double xm, double ym, double tm, float &D,
-                                float (&bz)[NT]) {
+            // Per pair: each vector's squared distance in its own spatial scale,
+            // d2 cx_z in FP64 rounded once to FP32 (so that its triggering exponent
+            // r_m D is rounded as a single sweep at that vector rounds it), and its
+            // background term.
+            auto pair_terms = [&](double xn_, double yn_, double tn_, double xm, double ym, double tm,
+                                  float (&Dz)[NT], float (&bz)[NT]) {
                 const double dx = xn_ - xm, dy = yn_ - ym, dt = tn_ - tm;
                 const double d2 = fma(dy, dy, dx * dx);
-                D = float(d2);
                 const double dt2 = dt * dt;
 #pragma unroll
                 for (int z = 0; z < NT; ++z) {
+                    const double dz = (z == 0) ? d2 : d2 * a.cx[z];
+                    Dz[z] = float(dz);
                     if (UNI) {
                         const double a2 = (z == 0) ? dt2 : dt2 * a.ct2[z];
                         const float A = float(a2), Alo = float(a2 - double(A));
                         const float e = __builtin_amdgcn_exp2f(-A);
                         bz[z] = fmaf(-LN2F * Alo, e, e);
                     } else {
-                        const float A = (z == 0) ? float(fma(dt, dt, d2)) : float(fma(dt2, a.ct2[z], d2 * a.cx[z]));
+                        const float A = (z == 0) ? float(fma(dt, dt, d2)) : float(fma(dt2, a.ct2[z], dz));
                         bz[z] = __builtin_amdgcn_exp2f(-A);
                     }
                 }
+            };
+            // squared distances only (triggering terms of tiles without background terms)
+            auto dist_terms = [&](double xn_, double yn_, double xm, double ym, float (&Dz)[NT]) {
+                const double dx = xn_ - xm, dy = yn_ - ym;
+                const double d2 = fma(dy, dy, dx * dx);
+#pragma unroll
+                for (int z = 0; z < NT; ++z)
+                    Dz[z] = float((z == 0) ? d2 : d2 * a.cx[z]);
             };
 
             if (cls != MIXED) {
@@ -1242,11 +1255,12 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32_batch(PairBatchF32
                         const double xm = T.x[m], ym = T.y[m], tm = T.t[m];
 #pragma unroll
                         for (int q = 0; q < KT; ++q) {
-                            float D, bz[NT];
-                            bg_terms(xn[q], yn[q], tsn[q], xm, ym, tm, D, bz);
+                            float Dz[NT], bz[NT];
+                            pair_terms(xn[q], yn[q], tsn[q], xm, ym, tm, Dz, bz);
 #pragma unroll
                             for (int z = 0; z < NT; ++z) {
                                 const float2 rm = T.r[z][m], vm = T.v[z][m];
+                                const float D = Dz[z];
                                 const float t1 = fmaf(rm.y, D, rm.x * D);
                                 const float E = __builtin_amdgcn_exp2f(-t1);
                                 const float p = fmaf(vm.y, E, vm.x * E);
@@ -1260,10 +1274,12 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32_batch(PairBatchF32
                         const double xm = T.x[m], ym = T.y[m];
 #pragma unroll
                         for (int q = 0; q < KT; ++q) {
-                            const float D = geom_d(xn[q], yn[q], xm, ym);
+                            float Dz[NT];
+                            dist_terms(xn[q], yn[q], xm, ym, Dz);
 #pragma unroll
                             for (int z = 0; z < NT; ++z) {
                                 const float2 rm = T.r[z][m], vm = T.v[z][m];
+                                const float D = Dz[z];
                                 const float t1 = fmaf(rm.y, D, rm.x * D);
                                 const float E = __builtin_amdgcn_exp2f(-t1);
                                 f[q][z][1] += fmaf(vm.y, E, vm.x * E);
@@ -1322,8 +1338,8 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32_batch(PairBatchF32
                             const double xm = T.x[m], ym = T.y[m], tm = T.t[m];
 #pragma unroll
                             for (int q = 0; q < KT; ++q) {
-                                float D, bz[NT];
-                                bg_terms(xn[q], yn[q], tsn[q], xm, ym, tm, D, bz);
+                                float Dz[NT], bz[NT];
+                                pair_terms(xn[q], yn[q], tsn[q], xm, ym, tm, Dz, bz);
 #pragma unroll
                                 for (int z = 0; z < NT; ++z)
                                     f[q][z][0] += bz[z];
@@ -1366,12 +1382,13 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32_batch(PairBatchF32
                         const int gm = T.dg[m].g;
 #pragma unroll
                         for (int q = 0; q < KT; ++q) {
-                            float D, bz[NT];
-                            bg_terms(xn[q], yn[q], tsn[q], xm, ym, tm, D, bz);
+                            float Dz[NT], bz[NT];
+                            pair_terms(xn[q], yn[q], tsn[q], xm, ym, tm, Dz, bz);
                             const double dt = tsn[q] - tm;
 #pragma unroll
                             for (int z = 0; z < NT; ++z) {
                                 const float2 rm = T.r[z][m];
+                                const float D = Dz[z];
                                 const float b = (gm != gn[q]) ? bz[z] : 0.0f;
                                 const float t1 = fmaf(rm.y, D, rm.x * D);
                                 const float arg = float(fma(a.w2[z], dt, double(t1)));
@@ -2415,16 +2432,17 @@ int run_batch(const hawkes_events *ev, const hawkes_theta *th, int64_t num_theta
         const double tau_sp0 = S.uniform ? t0->h0 : t0->tau_x;
         for (int z = 0; z < MAX_FUSED_THETA; ++z) {
             const hawkes_theta *tz = t0 + z;
+            const double tau_sp = S.uniform ? tz->h0 : tz->tau_x;
             if (z > 0) {
-                // theta z's r_m and v_m with theta 0's position scale
-                const double rr = (tau_sp0 / tz->h0) * (tau_sp0 / tz->h0);
+                // theta z's r_m (for its own position scale) and v_m
+                const double rr = (tau_sp / tz->h0) * (tau_sp / tz->h0);
                 hipLaunchKernelGGL(k_stage_f32_rv, dim3(S.stage_blocks), dim3(256), 0, stream, ev->t, ev->s, S.n,
                                    L.n_pad, rr, tz->omega, S.tile, r2 + int64_t(z) * L.n_pad,
                                    v2 + int64_t(z) * L.n_pad);
                 if ((rc = check_launch("stage_f32_rv")) != HAWKES_OK)
                     return rc;
             }
-            a.cx[z] = (t0->tau_x / tz->tau_x) * (t0->tau_x / tz->tau_x);
+            a.cx[z] = (tau_sp0 / tau_sp) * (tau_sp0 / tau_sp);
             a.ct2[z] = (t0->tau_t / tz->tau_t) * (t0->tau_t / tz->tau_t);
             a.omega[z] = tz->omega;
             a.w2[z] = tz->omega * LOG2E / sc0.st;
