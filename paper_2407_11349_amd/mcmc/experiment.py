@@ -190,7 +190,7 @@ def run_mh(target: HawkesCutTarget, z0, inv_mass, n_iter: int, it0: int, n_adapt
     z = np.asarray(z0, dtype=np.float64)
     for it in range(n_adapt):
         target.resample(it0 + it)
-        z, _ = mh.sweep(z, target.logp(z), adapt_rate=0.5 / np.sqrt(it + 1.0))
+        z, _ = mh.sweep(z, None, adapt_rate=0.5 / np.sqrt(it + 1.0))
     mh.accepts[:] = 0
     mh.tries[:] = 0
     n0, g0 = target.n_loglik, target.n_grad
@@ -199,7 +199,7 @@ def run_mh(target: HawkesCutTarget, z0, inv_mass, n_iter: int, it0: int, n_adapt
     draws = []
     for it in range(n_iter):
         target.resample(it0 + n_adapt + it)
-        z, _ = mh.sweep(z, target.logp(z))
+        z, _ = mh.sweep(z)  # the current point's density under the new draw, paired with the first proposal
         draws.append(z.copy())
         if log and (it + 1) % 500 == 0:
             log(f"mh {it + 1}/{n_iter}: acceptance {np.round(mh.acceptance(), 2)}")

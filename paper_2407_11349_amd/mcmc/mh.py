@@ -5,7 +5,9 @@ Each sweep updates the log-parameters z = log theta one coordinate at a time wit
 Gaussian random-walk proposal; every proposal costs one exact log-density (the
 forward-only sweep, no gradient).  The proposal scales adapt during warm-up
 towards the acceptance rate 0.44 that suits one-dimensional random walks, and are
-fixed afterwards.
+fixed afterwards.  Under the cut posterior each sweep starts after a new
+latent-location draw, so the current point's density is recomputed; with a target
+that offers `logp_batch` it is evaluated together with the first proposal.
 """
 
 from __future__ import annotations
@@ -23,14 +25,22 @@ class UnivariateMH:
         self.accepts = np.zeros(dim)
         self.tries = np.zeros(dim)
 
-    def sweep(self, z, logp: float, adapt_rate: float = 0.0):
-        """One pass over the coordinates from (z, logp = log density at z); returns the new pair.
-        With adapt_rate > 0 each coordinate's log scale moves by adapt_rate * (accepted - target)."""
+    def sweep(self, z, logp: float | None = None, adapt_rate: float = 0.0):
+        """One pass over the coordinates from (z, logp = log density at z, or None to compute it);
+        returns the new pair.  With adapt_rate > 0 each coordinate's log scale moves by
+        adapt_rate * (accepted - target)."""
         z = np.asarray(z, dtype=np.float64).copy()
+        batch = getattr(self.target, "logp_batch", None)
         for i in range(self.dim):
             prop = z.copy()
             prop[i] += self.scales[i] * self.rng.normal()
-            lp = self.target.logp(prop)
+            if logp is None:
+                if batch is not None:
+                    logp, lp = (float(v) for v in batch([z, prop]))
+                else:
+                    logp, lp = self.target.logp(z), self.target.logp(prop)
+            else:
+                lp = self.target.logp(prop)
             acc = bool(np.isfinite(lp) and np.log(self.rng.uniform()) < lp - logp)
             if acc:
                 z, logp = prop, lp

@@ -196,3 +196,27 @@ def test_delayed_acceptance_lazy_refresh_pairs_exact_values():
             assert da.stats["paired_exact"] > 100
             assert tgt.batches and set(tgt.batches) == {2}
     np.testing.assert_allclose(chains[0], chains[1], rtol=0, atol=1e-12)
+
+
+def test_univariate_mh_pairs_the_refreshed_density_with_the_first_proposal():
+    """After a new draw the current point's density and the first proposal's come from one
+    two-vector call; the chain equals the one that evaluates them one at a time."""
+    from paper_2407_11349_amd.mcmc.mh import UnivariateMH
+
+    _, mu, C = _target(5)
+    chains = []
+    for paired in (True, False):
+        tgt = DrawTarget(mu, np.linalg.inv(C))
+        if not paired:
+            tgt.logp_batch = None  # the sampler then calls logp twice
+        mh = UnivariateMH(tgt, scales=np.full(6, 0.3), rng=np.random.default_rng(9))
+        z = np.zeros(6)
+        zs = []
+        for it in range(300):
+            tgt.resample(it)
+            z, _ = mh.sweep(z)
+            zs.append(z.copy())
+        chains.append(np.array(zs))
+        if paired:
+            assert tgt.batches == [2] * 300
+    np.testing.assert_allclose(chains[0], chains[1], rtol=0, atol=0)
