@@ -106,33 +106,40 @@ __device__ inline float gelu_d2(float x) { return K_INV_SQRT_2PI * expf(-0.5f * 
 __device__ inline float matvec_kmajor(const uint16_t *__restrict__ M, const float *v, int j)
 {
     float acc = 0.0f;
-#pragma unroll 8
+#pragma unroll 32
     for (int k = 0; k < H; ++k)
         acc = fmaf(bf16_to_f32(M[k * H + j]), v[k], acc);
     return acc;
 }
 
-// block-wide sum of one value per thread (256 threads), result in every thread
-__device__ inline float block_sum(float v, float *red)
+// Block-wide sums of seven values per thread (256 threads) in one pairwise
+// tree, results in every thread.
+constexpr int NS7 = 7;
+__device__ inline void block_sum7(const float v[NS7], float (*red)[H], float out[NS7])
 {
     const int j = threadIdx.x;
-    red[j] = v;
+#pragma unroll
+    for (int z = 0; z < NS7; ++z)
+        red[z][j] = v[z];
     __syncthreads();
     for (int w = H / 2; w > 0; w >>= 1) {
         if (j < w)
-            red[j] += red[j + w];
+#pragma unroll
+            for (int z = 0; z < NS7; ++z)
+                red[z][j] += red[z][j + w];
         __syncthreads();
     }
-    const float r = red[0];
+#pragma unroll
+    for (int z = 0; z < NS7; ++z)
+        out[z] = red[z][0];
     __syncthreads();
-    return r;
 }
 
 // Value and input gradient, one workgroup per sample.
 __global__ __launch_bounds__(H) void k_mlp_forward(Net net, const float *__restrict__ z, int64_t B,
                                                    float *__restrict__ f_out, float *__restrict__ gz_out)
 {
-    __shared__ float sz[DZ], a1[H], a2[H], d[H], red[H];
+    __shared__ float sz[DZ], a1[H], a2[H], d[H], red[NS7][H];
     const int j = threadIdx.x;
     const int64_t b = blockIdx.x;
     if (j < DZ)
@@ -152,7 +159,7 @@ __global__ __launch_bounds__(H) void k_mlp_forward(Net net, const float *__restr
     __syncthreads();
     const float h3 = bf16_to_f32(w[OB3 + j]) + matvec_kmajor(net.wt3, a2, j);
     const float w4 = bf16_to_f32(w[OW4 + j]);
-    const float f = block_sum(w4 * gelu(h3), red) + bf16_to_f32(w[OB4]);
+    const float vf = w4 * gelu(h3);  // summed with the input gradient below
     d[j] = w4 * gelu_d1(h3);
     __syncthreads();
     const float d2 = s2 * matvec_kmajor(w + OW3, d, j);  // (W3^T d3)_j: W3 row-major is k-major for W3^T
@@ -160,10 +167,14 @@ __global__ __launch_bounds__(H) void k_mlp_forward(Net net, const float *__restr
     d[j] = d2;
     __syncthreads();
     const float d1 = s1 * matvec_kmajor(w + OW2, d, j);
-    float g[DZ];
+    float v7[NS7], s7[NS7];
+    v7[0] = vf;
 #pragma unroll
     for (int i = 0; i < DZ; ++i)
-        g[i] = block_sum(bf16_to_f32(w[OW1 + j * DZ + i]) * d1, red);
+        v7[1 + i] = bf16_to_f32(w[OW1 + j * DZ + i]) * d1;
+    block_sum7(v7, red, s7);
+    const float f = s7[0] + bf16_to_f32(w[OB4]);
+    const float *g = s7 + 1;
     if (j == 0) {
         f_out[b] = f;
         if (gz_out)
@@ -187,7 +198,7 @@ __global__ __launch_bounds__(H) void k_mlp_train_sample(Net net, const float *__
                                                         const float *__restrict__ y, const float *__restrict__ g,
                                                         int64_t B, float lam, TrainWs ws)
 {
-    __shared__ float sz[DZ], sr[DZ], v1[H], v2[H], red[H];
+    __shared__ float sz[DZ], sr[DZ], v1[H], v2[H], red[NS7][H];
     const int j = threadIdx.x;
     const int64_t b = blockIdx.x;
     const uint16_t *w = net.w;
@@ -210,7 +221,7 @@ __global__ __launch_bounds__(H) void k_mlp_train_sample(Net net, const float *__
     const float h3 = bf16_to_f32(w[OB3 + j]) + matvec_kmajor(net.wt3, v2, j);
     const float a3 = gelu(h3), s3 = gelu_d1(h3);
     const float w4 = bf16_to_f32(w[OW4 + j]);
-    const float f = block_sum(w4 * a3, red) + bf16_to_f32(w[OB4]);
+    const float vf = w4 * a3;  // summed with the input gradient below
     // input gradient
     v1[j] = w4 * s3;
     __syncthreads();
@@ -218,10 +229,16 @@ __global__ __launch_bounds__(H) void k_mlp_train_sample(Net net, const float *__
     v2[j] = d2;
     __syncthreads();
     const float d1 = s1 * matvec_kmajor(w + OW2, v2, j);
-    float rr[DZ];
+    float v7[NS7], s7[NS7], rr[DZ];
+    v7[0] = vf;
 #pragma unroll
     for (int i = 0; i < DZ; ++i)
-        rr[i] = block_sum(bf16_to_f32(w[OW1 + j * DZ + i]) * d1, red) - g[b * DZ + i];
+        v7[1 + i] = bf16_to_f32(w[OW1 + j * DZ + i]) * d1;
+    block_sum7(v7, red, s7);
+    const float f = s7[0] + bf16_to_f32(w[OB4]);
+#pragma unroll
+    for (int i = 0; i < DZ; ++i)
+        rr[i] = s7[1 + i] - g[b * DZ + i];
     const float e = f - y[b];
     if (j < DZ)
         sr[j] = rr[j];

@@ -231,3 +231,23 @@ def test_cut_target_logp_batch_matches_logp():
         assert mixed[1] == -np.inf and mixed[2] == -np.inf
         assert mixed[0] == pytest.approx(single[0], rel=1e-14)
         assert mixed[3] == pytest.approx(single[1], rel=SECOND_TOL)
+
+
+def test_batch_rescues_underflow_limited_rows_per_vector():
+    """Narrow kernels put event 1's rate at ~1e-36, below what FP32 sums hold: each vector's
+    finalize must put the row on its own rescue list and recompute it in FP64 (the list is
+    restarted between the vectors of a pair)."""
+    t = np.array([1.0, 1.5])
+    x = np.array([0.0, 0.438])
+    y = np.array([0.0, 0.0])
+    s = np.array([1.0, 1.0])
+    narrow = np.array([1.0, 0.05, 0.05, 1.0, 0.05, 1.0])
+    wide = synth.theta_default()
+    dev = hk.DeviceEvents.from_arrays(t, x, y, s)
+    for ths in ([narrow, wide], [wide, narrow], [narrow, narrow * 1.01]):
+        got = _batch(dev, ths, "fp32")
+        for j, th in enumerate(ths):
+            ref, _ = oracle.loglik(t, x, y, s, th)
+            single = _single(dev, th, "fp32")
+            assert abs(got[j] - ref) <= 5e-7, (j, got[j], ref)
+            assert abs(got[j] - single) <= 1e-12 * abs(single), (j, got[j], single)
