@@ -32,6 +32,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "loglik+grad pairs/s at N=1M, FP32 vs FP64; ESS/s surrogate-HMC vs plain HMC"
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector: 256 CU x 2.4 GHz x 256 FLOP/clk
+# v_exp_f32 issue rate measured on the box (31.9 lane-ops/clk/CU, profiles/valu_rates_gfx950.md)
+EXP_PEAK_PER_S = 1.958e13
 # algorithmic FLOP per pair of the fused sweep (FMA = 2, add/sub/mul = 1; exp counted apart):
 # background 15 for every pair, triggering 10 more for causal pairs
 FLOP_BG, FLOP_TRIG = 15, 10
@@ -51,22 +53,34 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic() -> float | None:
-    """HBM bytes per pair-sweep launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "pair_f32_n1m_traffic.md")
+def profile_fields(name: str) -> dict:
+    """The two-column table rows of a committed rocprofv3 summary under profiles/, if its counters
+    were taken on the current kernel source (its `kernel source hash` row); else {}."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
-        return None
+        return {}
     fields = {}
     for line in open(path):
         if line.startswith("|") and line.count("|") >= 3:
             cells = [c.strip() for c in line.strip().strip("|").split("|")]
             if len(cells) >= 2:
-                fields[cells[0]] = cells[1]
-    if fields.get("kernel source hash") != kernel_source_hash():
-        return None
+                fields.setdefault(cells[0], cells[1])
+    return fields if fields.get("kernel source hash") == kernel_source_hash() else {}
+
+
+def measured_traffic() -> float | None:
+    """HBM bytes per pair-sweep launch from the committed counter summary (None if stale)."""
     try:
-        return float(fields["HBM bytes per launch"])
+        return float(profile_fields("pair_f32_n1m_traffic.md")["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def issue_bound_ms() -> float | None:
+    """The pair sweep's VALU issue bound at 2.4 GHz (its counted instruction mix weighted by the
+    measured single-kind issue rates) from the committed SQ counter summary (None if stale)."""
+    try:
+        return float(profile_fields("pair_f32_n1m_valu_mix.md")["issue bound at 2.4 GHz (ms)"])
     except (KeyError, ValueError):
         return None
 
@@ -318,9 +332,14 @@ def main():
                      "executed": {"flop_per_launch": flop_executed, "exp_per_launch": exp_executed,
                                   "achieved": flop_executed / (kms / 1e3) / 1e12,
                                   "frac": flop_executed / (kms / 1e3) / 1e12 / PEAK_FP32_TFLOPS,
+                                  "exp_per_s": exp_executed / (kms / 1e3),
+                                  "exp_frac_of_measured_exp_peak": exp_executed / (kms / 1e3) / EXP_PEAK_PER_S,
+                                  "issue_bound_ms": issue_bound_ms(),
+                                  "frac_of_issue_bound": (issue_bound_ms() / kms) if issue_bound_ms() else None,
                                   "note": "FLOP the symmetric sweep performs (each background term "
                                           "once per pair, plus column sums); frac above uses the "
-                                          "fixed per-ordered-pair count"}},
+                                          "fixed per-ordered-pair count; issue bound from the SQ "
+                                          "instruction counters of this kernel source"}},
     }
 
     if not args.no_fp64:

@@ -1510,8 +1510,43 @@ struct PairF64 {
     double *prow, *pcol;     // row partials [num_gc][6][rows_pad], column partials [num_gr][3][rows_pad]
     int n, row_begin, row_end, rows_pad, num_tiles, num_tb;
     int rr, ct, num_gr, num_gc, sym;
-    double ax, at, qh, omega;  // 1/(2 tau_x^2), 1/(2 tau_t^2), 1/(2 h0^2), omega
+    double ax, at, qh, omega;  // log2(e) times: 1/(2 tau_x^2), 1/(2 tau_t^2), 1/(2 h0^2), omega
 };
+
+// 2^y for y <= 0 in FP64 (the pair terms of the FP64 sweep, whose exponents are
+// formed in units of log2): y = k + f with k = rint(y) and |f| <= 1/2, 2^f from
+// the Taylor series of e^(f ln 2) to degree 12 (truncation below 2.4e-16
+// relative for |f ln 2| <= 0.35, of one sign and about 1e-18 on average over
+// f) by Horner's rule, then scaled by 2^k (the
+// classical reduction of Cody and Waite, with the reduction exact here because
+// the base is 2).  Exponents below -2000 give 0.
+constexpr double exp2_taylor_coef(int n)
+{
+    double c = 1.0;
+    for (int i = 1; i <= n; ++i)
+        c = c * 0.69314718055994530942 / double(i);
+    return c;
+}
+__device__ __forceinline__ double exp2_nonpos(double y)
+{
+    y = fmax(y, -2000.0);
+    const double k = rint(y);
+    const double f = y - k;
+    double p = exp2_taylor_coef(12);
+    p = fma(p, f, exp2_taylor_coef(11));
+    p = fma(p, f, exp2_taylor_coef(10));
+    p = fma(p, f, exp2_taylor_coef(9));
+    p = fma(p, f, exp2_taylor_coef(8));
+    p = fma(p, f, exp2_taylor_coef(7));
+    p = fma(p, f, exp2_taylor_coef(6));
+    p = fma(p, f, exp2_taylor_coef(5));
+    p = fma(p, f, exp2_taylor_coef(4));
+    p = fma(p, f, exp2_taylor_coef(3));
+    p = fma(p, f, exp2_taylor_coef(2));
+    p = fma(p, f, exp2_taylor_coef(1));
+    p = fma(p, f, 1.0);
+    return ldexp(p, int(k));
+}
 
 __device__ __forceinline__ double row_rotate_f64(double v)
 {
@@ -1640,7 +1675,7 @@ __global__ __launch_bounds__(WG) void k_pair_f64(PairF64 a)
                     const bool use_b = use_bg_all || (gm != gn[q]);
                     const bool use_g = (cls == CAUSAL) || (cls == MIXED && gm < gn[q]);
                     if (use_b) {
-                        const double bb = exp(-(a.ax * d2 + a.at * dt * dt));
+                        const double bb = exp2_nonpos(-(a.ax * d2 + a.at * dt * dt));
                         acc[q][0] += bb;
                         c0 += bb;
                         if (GRAD) {
@@ -1651,7 +1686,7 @@ __global__ __launch_bounds__(WG) void k_pair_f64(PairF64 a)
                         }
                     }
                     if (use_g) {
-                        const double e = um * exp(-(um * a.qh * d2 + a.omega * dt));
+                        const double e = um * exp2_nonpos(-(um * a.qh * d2 + a.omega * dt));
                         acc[q][3] += e;
                         if (GRAD) {
                             acc[q][4] += e * (um * d2);
@@ -2345,10 +2380,11 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
         a.num_gr = S.grid_gr;
         a.num_gc = S.grid_gc;
         a.sym = S.sym ? 1 : 0;
-        a.ax = uniform ? 0.0 : 1.0 / (2.0 * th->tau_x * th->tau_x);  // uniform background: no spatial factor
-        a.at = 1.0 / (2.0 * th->tau_t * th->tau_t);
-        a.qh = 1.0 / (2.0 * h0 * h0);
-        a.omega = omega;
+        // exponents in units of log2 (the sweep's exp2); uniform background: no spatial factor
+        a.ax = uniform ? 0.0 : LOG2E / (2.0 * th->tau_x * th->tau_x);
+        a.at = LOG2E / (2.0 * th->tau_t * th->tau_t);
+        a.qh = LOG2E / (2.0 * h0 * h0);
+        a.omega = omega * LOG2E;
         if (g_timing && (rc = record_event(g_ev_start, stream)) != HAWKES_OK)
             return rc;
         if (grad)
