@@ -1563,7 +1563,7 @@ __device__ __forceinline__ double row_rotate_f64(double v)
 template <bool GRAD>
 __global__ __launch_bounds__(WG) void k_pair_f64(PairF64 a)
 {
-    __shared__ double lx[2][TS], ly[2][TS], lt[2][TS], lu[2][TS];
+    __shared__ double lx[2][TS], ly[2][TS], lt[2][TS], lu[2][TS], lq[2][TS];  // lq: u_m qh
     __shared__ int lg[2][TS];
     __shared__ double lcol[3][NW][TS];  // per-wave column sums of the tile just swept
 
@@ -1590,19 +1590,21 @@ __global__ __launch_bounds__(WG) void k_pair_f64(PairF64 a)
         }
     }
 
-    auto fetch = [&](int j, double &fx, double &fy, double &ft, double &fu, int &fg) {
+    auto fetch = [&](int j, double &fx, double &fy, double &ft, double &fu, double &fq, int &fg) {
         if (j < a.n) {
             fx = a.x[j];
             fy = a.y[j];
             ft = a.t[j];
             const double sj = a.s[j];
             fu = 1.0 / (sj * sj);
+            fq = fu * a.qh;
             fg = a.g[j];
         } else {
             fx = PAD_COORD;
             fy = PAD_COORD;
             ft = PAD_TIME;
             fu = 0.0;
+            fq = 0.0;
             fg = INT_MAX;
         }
     };
@@ -1640,13 +1642,14 @@ __global__ __launch_bounds__(WG) void k_pair_f64(PairF64 a)
         const int k1 = (kg1 < k_end) ? kg1 : k_end;
 
         if (k0 < k1) {
-            double fx, fy, ft, fu;
+            double fx, fy, ft, fu, fq;
             int fg;
-            fetch(k0 * TS + tid, fx, fy, ft, fu, fg);
+            fetch(k0 * TS + tid, fx, fy, ft, fu, fq, fg);
             lx[0][tid] = fx;
             ly[0][tid] = fy;
             lt[0][tid] = ft;
             lu[0][tid] = fu;
+            lq[0][tid] = fq;
             lg[0][tid] = fg;
         }
         __syncthreads();
@@ -1654,10 +1657,10 @@ __global__ __launch_bounds__(WG) void k_pair_f64(PairF64 a)
         for (int k = k0; k < k1; ++k) {
             const int buf = (k - k0) & 1;
             const bool more = (k + 1 < k1);
-            double px = 0, py = 0, pt = 0, pu = 0;
+            double px = 0, py = 0, pt = 0, pu = 0, pq = 0;
             int pg = 0;
             if (more)
-                fetch((k + 1) * TS + tid, px, py, pt, pu, pg);
+                fetch((k + 1) * TS + tid, px, py, pt, pu, pq, pg);
 
             const double first = a.tile[3 * k + 0], last = a.tile[3 * k + 1];
             const int cls = (last < t_lo) ? CAUSAL : ((first > t_hi) ? ANTI : MIXED);
@@ -1666,31 +1669,34 @@ __global__ __launch_bounds__(WG) void k_pair_f64(PairF64 a)
             // background and triggering terms of source m for the lane's targets
             auto pair = [&](int m, bool use_bg_all, double &c0, double &c1, double &c2) {
                 const double xm = lx[buf][m], ym = ly[buf][m], tm = lt[buf][m], um = lu[buf][m];
+                const double uq = lq[buf][m];
                 const int gm = lg[buf][m];
 #pragma unroll
                 for (int q = 0; q < KT; ++q) {
                     const double dx = xn[q] - xm, dy = yn[q] - ym;
-                    const double d2 = dx * dx + dy * dy;
+                    const double d2 = fma(dy, dy, dx * dx);
                     const double dt = tn[q] - tm;
+                    const double dt2 = dt * dt;
                     const bool use_b = use_bg_all || (gm != gn[q]);
                     const bool use_g = (cls == CAUSAL) || (cls == MIXED && gm < gn[q]);
                     if (use_b) {
-                        const double bb = exp2_nonpos(-(a.ax * d2 + a.at * dt * dt));
+                        const double bb = exp2_nonpos(-fma(a.at, dt2, a.ax * d2));
                         acc[q][0] += bb;
                         c0 += bb;
                         if (GRAD) {
-                            acc[q][1] += bb * d2;
-                            acc[q][2] += bb * dt * dt;
-                            c1 += bb * d2;
-                            c2 += bb * dt * dt;
+                            const double bd = bb * d2, bt = bb * dt2;
+                            acc[q][1] += bd;
+                            acc[q][2] += bt;
+                            c1 += bd;
+                            c2 += bt;
                         }
                     }
                     if (use_g) {
-                        const double e = um * exp2_nonpos(-(um * a.qh * d2 + a.omega * dt));
+                        const double e = um * exp2_nonpos(-fma(uq, d2, a.omega * dt));
                         acc[q][3] += e;
                         if (GRAD) {
-                            acc[q][4] += e * (um * d2);
-                            acc[q][5] += e * dt;
+                            acc[q][4] = fma(e, um * d2, acc[q][4]);
+                            acc[q][5] = fma(e, dt, acc[q][5]);
                         }
                     }
                 }
@@ -1738,6 +1744,7 @@ __global__ __launch_bounds__(WG) void k_pair_f64(PairF64 a)
                 ly[nb][tid] = py;
                 lt[nb][tid] = pt;
                 lu[nb][tid] = pu;
+                lq[nb][tid] = pq;
                 lg[nb][tid] = pg;
             }
             __syncthreads();
