@@ -87,6 +87,11 @@ namespace {
 #ifndef HAWKES_UJ
 #define HAWKES_UJ 2
 #endif
+// source-loop unrolling of the fused loglik+gradient sweep (more registers per
+// step, one more independent chain in flight)
+#ifndef HAWKES_UJ_GRAD
+#define HAWKES_UJ_GRAD 4
+#endif
 #define HK_STR(x) #x
 #define HK_UNROLL(n) _Pragma(HK_STR(unroll n))
 
@@ -562,7 +567,7 @@ __device__ __forceinline__ void stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70
 // no columns).
 //
 // At least this many waves per SIMD: the register budget the compiler must
-// fit (2 waves = 256 registers per lane).  KT = 2 needs ~163 and runs at 3.
+// fit (2 waves = 256 registers per lane).  KT = 2 needs ~164 and runs at 3.
 #ifndef HAWKES_WAVES_PER_EU
 #define HAWKES_WAVES_PER_EU 2
 #endif
@@ -584,6 +589,7 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
     __shared__ TileRecs lt2[2];
     __shared__ float lcol[2][3][NW][TS];  // per-wave column sums of the tile being swept
 
+    constexpr int UJ = GRAD ? HAWKES_UJ_GRAD : HAWKES_UJ;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15;
     const int gr = a.num_gr - 1 - int(blockIdx.x / unsigned(a.num_gc));  // latest row groups first
     const int gc = int(blockIdx.x % unsigned(a.num_gc));
@@ -815,13 +821,13 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
                     };
                     const int sub = m0 & ~15, s0 = m0 & 15;
                     if (trig_only) {
-                        HK_UNROLL(HAWKES_UJ)
+                        HK_UNROLL(UJ)
                         for (int j = 0; j < GS; ++j)
                             trig_pair(m0 + j);
                     } else if (cols) {
                         // 16-source rotation (row sums as in the plain causal loop): lane i
                         // takes source sub + ((i + step) mod 16) at step step of the subgroup
-                        HK_UNROLL(HAWKES_UJ)
+                        HK_UNROLL(UJ)
                         for (int j = 0; j < GS; ++j) {
                             float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
                             causal_pair(sub + ((li + s0 + j) & 15), c0, c1, c2);
@@ -858,13 +864,13 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
                         }
                         e0 = e1 = e2 = 0.0f;
                     } else if (causal) {
-                        HK_UNROLL(HAWKES_UJ)
+                        HK_UNROLL(UJ)
                         for (int j = 0; j < GS; ++j) {
                             float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
                             causal_pair(m0 + j, c0, c1, c2);  // column sums unused
                         }
                     } else {
-                        HK_UNROLL(HAWKES_UJ)
+                        HK_UNROLL(UJ)
                         for (int j = 0; j < GS; ++j) {
                             const int m = m0 + j;
                             const double xm = sx[m], ym = sy[m], tm = st[m];

@@ -1,7 +1,8 @@
 """Build and time compile-time shapes of the FP32 pair sweep.
 
 Each shape is the library compiled with other values of the macros
-HAWKES_KT (target rows per lane), HAWKES_UJ (unroll of the source loop),
+HAWKES_KT (target rows per lane), HAWKES_UJ_GRAD / HAWKES_UJ (unroll of the
+source loop in the loglik+gradient sweep / the loglik-only sweeps),
 HAWKES_GS (FP32 terms per FP64 fold) and HAWKES_WAVES_PER_EU (register
 budget), into paper_2407_11349_amd/_variants/.  Every shape is timed with the
 library's own HIP-event hook on the 1e6-event, 1200-day workload (FP32
@@ -29,8 +30,8 @@ OUT = Path(__file__).resolve().parent / "_variants"
 # name -> macro definitions
 SHAPES = {
     "kt2": {"HAWKES_KT": 2},
-    "kt2_uj1": {"HAWKES_KT": 2, "HAWKES_UJ": 1},
-    "kt2_uj4": {"HAWKES_KT": 2, "HAWKES_UJ": 4},
+    "kt2_uj1": {"HAWKES_KT": 2, "HAWKES_UJ_GRAD": 1},
+    "kt2_uj2": {"HAWKES_KT": 2, "HAWKES_UJ_GRAD": 2},
     "kt2_w3": {"HAWKES_KT": 2, "HAWKES_WAVES_PER_EU": 3},
     "kt1": {"HAWKES_KT": 1},
     "kt4": {"HAWKES_KT": 4},
