@@ -56,6 +56,37 @@ int hawkes_mlp_store(const void *d_state, float *d_params, void *stream);
 int hawkes_mlp_forward(const void *d_state, const float *d_z, int64_t batch, float *d_f, float *d_gz,
                        void *stream);
 
+/* In/out record of hawkes_mlp_leapfrog (device memory, FP64; log-parameters z
+ * of dimension 6).  The surrogate log posterior is
+ *   s(z) = s_y f((z - m_z) / s_z) + m_y - z.z / (2 prior_var),
+ * the network's value f rescaled to a log-likelihood plus independent
+ * N(0, prior_var) priors on the z_i. */
+typedef struct hawkes_mlp_leapfrog_io {
+    double z[6];          /* in: start point; out: end point */
+    double p[6];          /* in: momentum at the start; out: at the end */
+    double grad[6];       /* in: ds/dz at the start point; out: at the end point */
+    double inv_mass[6];   /* diagonal inverse mass matrix */
+    double m_z[6], s_z[6]; /* input standardisation (s_z > 0) */
+    double m_y, s_y;      /* output scale */
+    double prior_var;     /* prior variance of each z_i */
+    double eps;           /* step size */
+    double s;             /* out: s at the end point; -inf if a step left the finite range */
+    double status;        /* out: 1 if every step was finite, else 0 */
+} hawkes_mlp_leapfrog_io;
+
+/* A leapfrog trajectory of n_steps steps (1..4096) of H(z, p) = -s(z) +
+ * p' M^-1 p / 2 on the surrogate log posterior above, run by one workgroup
+ * without returning to the host: the stage-1 proposal of delayed-acceptance
+ * HMC (Christen and Fox) on the network that stands in for the exact
+ * likelihood.  Half a momentum step, then per step a position step, s and
+ * ds/dz from the network (value and input gradient, as hawkes_mlp_forward
+ * computes them), and a momentum step (half a step after the last).
+ * Position and momentum updates are FP64 in the order
+ *   p += (eps / 2) grad;  z += (eps inv_mass) p;  p += eps grad,
+ * each product and sum rounded on its own.  A step whose s or gradient is not
+ * finite ends the trajectory with s = -inf and status 0. */
+int hawkes_mlp_leapfrog(const void *d_state, hawkes_mlp_leapfrog_io *d_io, int64_t n_steps, void *stream);
+
 /* Sobolev loss of a batch (d_z[batch][6], d_y[batch], d_g[batch][6]) into
  * d_loss[1], and its gradient with respect to the flat parameter vector into
  * d_grad[HAWKES_MLP_PARAMS] (if d_grad is NULL, into the workspace).  The

@@ -33,8 +33,10 @@ EXPORTS = (
     "hawkes_strerror", "hawkes_last_error",
     # include/hawkes_mlp.h
     "hawkes_mlp_state_bytes", "hawkes_mlp_workspace_bytes", "hawkes_mlp_load", "hawkes_mlp_store",
-    "hawkes_mlp_forward", "hawkes_mlp_loss_grad", "hawkes_mlp_adam_step",
+    "hawkes_mlp_forward", "hawkes_mlp_leapfrog", "hawkes_mlp_loss_grad", "hawkes_mlp_adam_step",
 )
+# hawkes_mlp_leapfrog_io: 42 doubles (z, p, grad, inv_mass, m_z, s_z: 6 each; m_y, s_y, prior_var, eps, s, status)
+LEAPFROG_IO_DOUBLES = 42
 MLP_PARAMS = 133633
 
 
@@ -87,6 +89,7 @@ def load(path: Path | str | None = None) -> ctypes.CDLL:
     lib.hawkes_mlp_load.argtypes = [vp, vp, vp]
     lib.hawkes_mlp_store.argtypes = [vp, vp, vp]
     lib.hawkes_mlp_forward.argtypes = [vp, vp, i64, vp, vp, vp]
+    lib.hawkes_mlp_leapfrog.argtypes = [vp, vp, i64, vp]
     lib.hawkes_mlp_loss_grad.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, vp, ctypes.c_size_t, vp, vp, vp]
     lib.hawkes_mlp_adam_step.argtypes = [vp, vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                          vp]
@@ -98,7 +101,8 @@ def load(path: Path | str | None = None) -> ctypes.CDLL:
                  "hawkes_resample_locations",
                  "hawkes_workspace_status", "hawkes_set_timing", "hawkes_last_pair_kernel_ms",
                  "hawkes_tune_target_workgroups", "hawkes_tune_symmetric_groups", "hawkes_mlp_load",
-                 "hawkes_mlp_store", "hawkes_mlp_forward", "hawkes_mlp_loss_grad", "hawkes_mlp_adam_step"):
+                 "hawkes_mlp_store", "hawkes_mlp_forward", "hawkes_mlp_leapfrog", "hawkes_mlp_loss_grad",
+                 "hawkes_mlp_adam_step"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -135,51 +135,143 @@ __device__ inline void block_sum7(const float v[NS7], float (*red)[H], float out
     __syncthreads();
 }
 
-// Value and input gradient, one workgroup per sample.
-__global__ __launch_bounds__(H) void k_mlp_forward(Net net, const float *__restrict__ z, int64_t B,
-                                                   float *__restrict__ f_out, float *__restrict__ gz_out)
+// Value and input gradient of one input sz[DZ] (in LDS) by the workgroup's
+// H threads; every thread returns f and g[DZ].  The scratch arrays are the
+// caller's LDS.
+struct FwdLds {
+    float a1[H], a2[H], d[H], red[NS7][H];
+};
+__device__ inline void value_and_grad(const Net &net, const float *sz, FwdLds &L, float &f, float g[DZ])
 {
-    __shared__ float sz[DZ], a1[H], a2[H], d[H], red[NS7][H];
     const int j = threadIdx.x;
-    const int64_t b = blockIdx.x;
-    if (j < DZ)
-        sz[j] = z[b * DZ + j];
-    __syncthreads();
     const uint16_t *w = net.w;
     float h1 = bf16_to_f32(w[OB1 + j]);
 #pragma unroll
     for (int i = 0; i < DZ; ++i)
         h1 = fmaf(bf16_to_f32(w[OW1 + j * DZ + i]), sz[i], h1);
-    a1[j] = gelu(h1);
+    L.a1[j] = gelu(h1);
     const float s1 = gelu_d1(h1);
     __syncthreads();
-    const float h2 = bf16_to_f32(w[OB2 + j]) + matvec_kmajor(net.wt2, a1, j);
-    a2[j] = gelu(h2);
+    const float h2 = bf16_to_f32(w[OB2 + j]) + matvec_kmajor(net.wt2, L.a1, j);
+    L.a2[j] = gelu(h2);
     const float s2 = gelu_d1(h2);
     __syncthreads();
-    const float h3 = bf16_to_f32(w[OB3 + j]) + matvec_kmajor(net.wt3, a2, j);
+    const float h3 = bf16_to_f32(w[OB3 + j]) + matvec_kmajor(net.wt3, L.a2, j);
     const float w4 = bf16_to_f32(w[OW4 + j]);
     const float vf = w4 * gelu(h3);  // summed with the input gradient below
-    d[j] = w4 * gelu_d1(h3);
+    L.d[j] = w4 * gelu_d1(h3);
     __syncthreads();
-    const float d2 = s2 * matvec_kmajor(w + OW3, d, j);  // (W3^T d3)_j: W3 row-major is k-major for W3^T
+    const float d2 = s2 * matvec_kmajor(w + OW3, L.d, j);  // (W3^T d3)_j: W3 row-major is k-major for W3^T
     __syncthreads();
-    d[j] = d2;
+    L.d[j] = d2;
     __syncthreads();
-    const float d1 = s1 * matvec_kmajor(w + OW2, d, j);
+    const float d1 = s1 * matvec_kmajor(w + OW2, L.d, j);
     float v7[NS7], s7[NS7];
     v7[0] = vf;
 #pragma unroll
     for (int i = 0; i < DZ; ++i)
         v7[1 + i] = bf16_to_f32(w[OW1 + j * DZ + i]) * d1;
-    block_sum7(v7, red, s7);
-    const float f = s7[0] + bf16_to_f32(w[OB4]);
-    const float *g = s7 + 1;
+    block_sum7(v7, L.red, s7);
+    f = s7[0] + bf16_to_f32(w[OB4]);
+#pragma unroll
+    for (int i = 0; i < DZ; ++i)
+        g[i] = s7[1 + i];
+}
+
+// Value and input gradient, one workgroup per sample.
+__global__ __launch_bounds__(H) void k_mlp_forward(Net net, const float *__restrict__ z, int64_t B,
+                                                   float *__restrict__ f_out, float *__restrict__ gz_out)
+{
+    __shared__ float sz[DZ];
+    __shared__ FwdLds L;
+    const int j = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    if (j < DZ)
+        sz[j] = z[b * DZ + j];
+    __syncthreads();
+    float f, g[DZ];
+    value_and_grad(net, sz, L, f, g);
     if (j == 0) {
         f_out[b] = f;
         if (gz_out)
             for (int i = 0; i < DZ; ++i)
                 gz_out[b * DZ + i] = g[i];
+    }
+}
+
+// A leapfrog trajectory on the surrogate posterior in one workgroup (the
+// stage-1 proposal of delayed-acceptance HMC): n_steps steps of
+// H(z, p) = -s(z) + p' M^-1 p / 2 with
+//   s(z) = s_y f((z - m_z) / s_z) + m_y - z.z / (2 prior_var),
+// from (z, p) with grad = ds/dz at z: half a momentum step, then per step a
+// position step, s and its gradient at the new point, and a full momentum
+// step (half a step after the last one).  Position and momentum updates are
+// FP64 without contraction, in the operation order of a host-side leapfrog
+// written the same way; a step whose s or gradient is not finite ends the
+// trajectory (s = -inf, no final half step).
+__global__ __launch_bounds__(H) void k_mlp_leapfrog(Net net, hawkes_mlp_leapfrog_io *io, int n)
+{
+#pragma clang fp contract(off)
+    __shared__ float sz[DZ];
+    __shared__ FwdLds L;
+    __shared__ double z[DZ], p[DZ], g[DZ];
+    __shared__ double sval;
+    __shared__ int ok;
+    const int j = threadIdx.x;
+    const double eps = io->eps, m_y = io->m_y, s_y = io->s_y, pv = io->prior_var;
+    double im = 0.0, mz = 0.0, szc = 1.0;
+    if (j < DZ) {
+        z[j] = io->z[j];
+        p[j] = io->p[j] + (0.5 * eps) * io->grad[j];
+        im = io->inv_mass[j];
+        mz = io->m_z[j];
+        szc = io->s_z[j];
+    }
+    if (j == 0) {
+        ok = 1;
+        sval = 0.0;
+    }
+    __syncthreads();
+    for (int step = 0; step < n; ++step) {
+        if (j < DZ) {
+            z[j] = z[j] + (eps * im) * p[j];
+            sz[j] = float((z[j] - mz) / szc);
+        }
+        __syncthreads();
+        float f, gz[DZ];
+        value_and_grad(net, sz, L, f, gz);
+        if (j < DZ)
+            g[j] = (double(gz[j]) * s_y) / szc - z[j] / pv;
+        if (j == 0) {
+            double zz = 0.0;
+            for (int i = 0; i < DZ; ++i)
+                zz = zz + z[i] * z[i];
+            sval = (double(f) * s_y + m_y) - (0.5 * zz) / pv;
+        }
+        __syncthreads();
+        if (j == 0) {
+            bool fin = isfinite(sval);
+            for (int i = 0; i < DZ; ++i)
+                fin = fin && isfinite(g[i]);
+            ok = fin ? 1 : 0;
+        }
+        __syncthreads();
+        if (!ok)
+            break;
+        if (j < DZ && step + 1 < n)
+            p[j] = p[j] + eps * g[j];
+        __syncthreads();
+    }
+    if (j < DZ) {
+        if (ok && n > 0)
+            p[j] = p[j] + (0.5 * eps) * g[j];
+        io->z[j] = z[j];
+        io->p[j] = p[j];
+        io->grad[j] = g[j];
+    }
+    if (j == 0) {
+        io->s = ok ? sval : -HUGE_VAL;
+        io->status = ok ? 1.0 : 0.0;
     }
 }
 
@@ -510,6 +602,17 @@ extern "C" int hawkes_mlp_forward(const void *d_state, const float *d_z, int64_t
     hipLaunchKernelGGL(k_mlp_forward, dim3(unsigned(batch)), dim3(H), 0, as_stream(stream), net_of(d_state), d_z,
                        batch, d_f, d_gz);
     return check_launch("mlp_forward");
+}
+
+extern "C" int hawkes_mlp_leapfrog(const void *d_state, hawkes_mlp_leapfrog_io *d_io, int64_t n_steps, void *stream)
+{
+    if (!d_state || !d_io || !aligned256(d_state) || n_steps < 1 || n_steps > 4096) {
+        set_error("mlp_leapfrog: invalid arguments (n_steps %lld)", (long long)n_steps);
+        return HAWKES_EINVAL;
+    }
+    hipLaunchKernelGGL(k_mlp_leapfrog, dim3(1), dim3(H), 0, as_stream(stream), net_of(d_state), d_io,
+                       int(n_steps));
+    return check_launch("mlp_leapfrog");
 }
 
 extern "C" int hawkes_mlp_loss_grad(const void *d_state, const float *d_z, const float *d_y, const float *d_g,

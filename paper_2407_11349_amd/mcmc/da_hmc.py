@@ -37,9 +37,12 @@ class DAState:
 
 class DelayedAcceptanceHMC:
     def __init__(self, target, surrogate_logp_and_grad, dim=6, n_leapfrog=20, step_size=0.05, inv_mass=None,
-                 rng=None, window=50, fallback_below=0.5):
+                 rng=None, window=50, fallback_below=0.5, trajectory=None):
+        """trajectory(z, p, grad, eps, inv_mass, n_steps) -> (z, p, s, grad), if given, runs the whole stage-1
+        leapfrog trajectory on the surrogate at once (e.g. on the GPU) instead of step by step here."""
         self.target = target
         self.sur = surrogate_logp_and_grad
+        self.trajectory = trajectory
         self.dim = dim
         self.n_leapfrog = n_leapfrog
         self.eps = step_size
@@ -89,7 +92,10 @@ class DelayedAcceptanceHMC:
                 return DAState(new.z, new.logp, s, sg), acc, "fallback"
             return st, acc, "fallback"
         p0 = self.rng.normal(size=self.dim) / np.sqrt(self.inv_mass)
-        z1, p1, s1, sg1 = leapfrog(st.z, p0, st.s_grad, self.eps, self.inv_mass, self.n_leapfrog, self.sur)
+        if self.trajectory is not None:
+            z1, p1, s1, sg1 = self.trajectory(st.z, p0, st.s_grad, self.eps, self.inv_mass, self.n_leapfrog)
+        else:
+            z1, p1, s1, sg1 = leapfrog(st.z, p0, st.s_grad, self.eps, self.inv_mass, self.n_leapfrog, self.sur)
         h0 = -st.s + kinetic(p0, self.inv_mass)
         h1 = -s1 + kinetic(p1, self.inv_mass)
         a1 = float(np.exp(min(0.0, h0 - h1))) if np.isfinite(h1) else 0.0

@@ -214,8 +214,12 @@ def run_da_hmc(target: HawkesCutTarget, sur: Surrogate, hmc: HMC, z0, n_iter: in
         ll, g = sur.value_and_grad(z)
         return float(ll[0]) - 0.5 * float(np.dot(z, z)) / prior_var, g[0] - np.asarray(z) / prior_var
 
+    def trajectory(z, p, grad, eps, inv_mass, n):
+        return sur.leapfrog(z, p, grad, eps, inv_mass, n, prior_var)
+
     da = DelayedAcceptanceHMC(target, sur_post, n_leapfrog=hmc.n_leapfrog, step_size=hmc.eps,
-                              inv_mass=hmc.inv_mass, rng=np.random.default_rng(11))
+                              inv_mass=hmc.inv_mass, rng=np.random.default_rng(11),
+                              trajectory=trajectory if hasattr(sur, "leapfrog") else None)
     n0, g0 = target.n_loglik, target.n_grad
     _sync()
     t0 = time.time()

@@ -62,6 +62,24 @@ class SurrogateNet:
                    "hawkes_mlp_forward")
         return f, gz
 
+    def leapfrog(self, z, p, grad, eps: float, inv_mass, n_steps: int, std: "Standardiser", prior_var: float):
+        """A whole leapfrog trajectory on the surrogate log posterior
+        s(z) = s_y f((z - m_z)/s_z) + m_y - z.z/(2 prior_var) in one kernel (hawkes_mlp_leapfrog);
+        returns (z, p, s, grad) at the end point as host arrays (s = -inf if a step was not finite)."""
+        L = _lib.LEAPFROG_IO_DOUBLES
+        if getattr(self, "_lf_host", None) is None:
+            self._lf_host = torch.empty(L, dtype=torch.float64).pin_memory()
+            self._lf_dev = torch.empty(L, dtype=torch.float64, device=self.device)
+        h = self._lf_host.numpy()
+        h[0:6], h[6:12], h[12:18], h[18:24] = z, p, grad, inv_mass
+        h[24:30], h[30:36] = std.m_z, std.s_z
+        h[36], h[37], h[38], h[39], h[40], h[41] = std.m_y, std.s_y, prior_var, eps, 0.0, 0.0
+        self._lf_dev.copy_(self._lf_host, non_blocking=True)
+        _lib.check(_lib.load().hawkes_mlp_leapfrog(self.state, self._lf_dev.data_ptr(), int(n_steps),
+                                                   _lib.stream_handle()), "hawkes_mlp_leapfrog")
+        out = self._lf_dev.cpu().numpy()
+        return out[0:6].copy(), out[6:12].copy(), float(out[40]), out[12:18].copy()
+
     def _workspace(self, B: int) -> int:
         if self._ws is None or self._ws_batch < B:
             nbytes = int(_lib.load().hawkes_mlp_workspace_bytes(B))
@@ -135,6 +153,10 @@ class Surrogate:
     def __init__(self, net: SurrogateNet, std: Standardiser):
         self.net = net
         self.std = std
+
+    def leapfrog(self, z, p, grad, eps, inv_mass, n_steps, prior_var):
+        """Leapfrog trajectory on the surrogate posterior (value + N(0, prior_var) priors), on the GPU."""
+        return self.net.leapfrog(z, p, grad, eps, inv_mass, n_steps, self.std, prior_var)
 
     def value_and_grad(self, logtheta: np.ndarray):
         z = torch.tensor(self.std.z(np.atleast_2d(logtheta)), dtype=torch.float32)

@@ -142,3 +142,52 @@ def test_training_up_to_one_offset_per_group():
     print(f"within-group rmse: grouped {e_g:.3f}, plain {e_p:.3f}, spread {spread:.3f}", flush=True)
     assert e_g < 0.1 * spread
     assert e_g < e_p
+
+
+def _std():
+    return Standardiser(m_z=np.array([-0.1, 1.9, 2.0, -2.1, 3.3, -3.1]),
+                        s_z=np.array([0.01, 0.02, 0.05, 0.03, 0.04, 0.08]), m_y=-5.4e5, s_y=4.0)
+
+
+def test_fused_leapfrog_equals_host_leapfrog():
+    """The one-kernel trajectory (hawkes_mlp_leapfrog) against the host leapfrog of the sampler
+    layer driving the same network call by call: positions, momenta and gradients bitwise (the
+    same FP64 operations in the same order, the same network arithmetic); s up to the order of
+    the prior's six-term sum."""
+    from paper_2407_11349_amd.mcmc.hmc import leapfrog
+
+    net = SurrogateNet(init_params(3))
+    std = _std()
+    sur = Surrogate(net, std)
+    prior_var = 100.0
+
+    def sur_post(z):
+        ll, g = sur.value_and_grad(z)
+        return float(ll[0]) - 0.5 * float(np.dot(z, z)) / prior_var, g[0] - np.asarray(z) / prior_var
+
+    rng = np.random.default_rng(7)
+    for trial in range(4):
+        z0 = std.m_z + std.s_z * rng.normal(size=6)
+        s0, g0 = sur_post(z0)
+        p0 = rng.normal(size=6)
+        inv_mass = std.s_z ** 2 * rng.uniform(0.5, 2.0, 6)
+        eps, n = 0.05 * (trial + 1), [1, 7, 20, 20][trial]
+        zh, ph, sh, gh = leapfrog(z0, p0, g0, eps, inv_mass, n, sur_post)
+        zf, pf, sf, gf = sur.leapfrog(z0, p0, g0, eps, inv_mass, n, prior_var)
+        assert np.array_equal(zf, zh) and np.array_equal(pf, ph) and np.array_equal(gf, gh), trial
+        assert sf == pytest.approx(sh, rel=1e-15, abs=0.0)
+
+
+def test_fused_leapfrog_stops_at_a_non_finite_step():
+    net = SurrogateNet(init_params(3))
+    std = _std()
+    sur = Surrogate(net, std)
+    z0 = std.m_z.copy()
+    ll, g = sur.value_and_grad(z0)
+    g0 = g[0] - z0 / 100.0
+    p0 = np.ones(6)
+    zf, pf, sf, gf = sur.leapfrog(z0, p0, g0, 1e200, np.ones(6), 5, 100.0)
+    assert sf == -np.inf
+    assert not np.all(np.isfinite(gf)) or not np.all(np.isfinite(zf))
+    # the momentum after the first half step only (no step completed)
+    np.testing.assert_array_equal(pf, p0 + (0.5 * 1e200) * g0)

@@ -125,3 +125,13 @@ def test_batch_host_validation(lib):
         _lib.theta_array([])
     with pytest.raises(ValueError):
         _lib.theta_array([good[:5]])
+
+
+def test_mlp_leapfrog_host_validation(lib):
+    fake = 0x200000  # never dereferenced: every call below fails host validation
+    assert lib.hawkes_mlp_leapfrog(None, fake, 20, None) == -1
+    assert lib.hawkes_mlp_leapfrog(fake, None, 20, None) == -1
+    assert lib.hawkes_mlp_leapfrog(fake + 8, fake, 20, None) == -1
+    assert lib.hawkes_mlp_leapfrog(fake, fake, 0, None) == -1
+    assert lib.hawkes_mlp_leapfrog(fake, fake, 4097, None) == -1
+    assert _lib.LEAPFROG_IO_DOUBLES * 8 == 336
