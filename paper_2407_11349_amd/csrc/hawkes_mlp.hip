@@ -12,6 +12,10 @@
 // and backward passes reads weights coalesced across the 256 lanes of a
 // workgroup.  All products accumulate in FP32.
 //
+// Inference: value and input gradient per sample (k_mlp_forward), or a whole
+// leapfrog trajectory on the surrogate posterior in one workgroup
+// (k_mlp_leapfrog, the stage-1 proposal of delayed-acceptance HMC).
+//
 // Training loss (value + gradient matching):
 //   L = (1/B) sum_b (f(z_b) - y_b)^2 + lambda |grad_z f(z_b) - g_b|^2.
 // Its parameter gradient uses d/dtheta [r . grad_z f] = d/dtheta [D_r f] for
