@@ -212,11 +212,13 @@ def run_ess(args, hk, synth, torch):
     dev = hk.DeviceEvents.from_arrays(ev.t, ev.x, ev.y, ev.s, device="cuda")
     county = torch.from_numpy(ev.county).cuda()
     rect = torch.from_numpy(ev.rect).cuda()
-    out = compare(dev, county, rect, n_burn=args.ess_burn, n_iter=args.ess_iter, n_warmup=args.ess_warmup, log=log)
+    out = compare(dev, county, rect, n_burn=args.ess_burn, n_iter=args.ess_iter, n_warmup=args.ess_warmup, log=log,
+                  replicate=args.ess_replicate)
     res = {"metric": "ESS/s surrogate-HMC vs plain HMC", "value": out["ess_per_s_ratio"], "unit": "ratio",
            "higher_is_better": True, "data": "synthetic",
            "config": {"workload": cfg.name, "n_events": ev.n, "burn_in": args.ess_burn, "iterations": args.ess_iter,
-                      "warmup": args.ess_warmup, "leapfrog": 20, "step": "resample X + sampler iteration"},
+                      "warmup": args.ess_warmup, "leapfrog": 20, "step": "resample X + sampler iteration",
+                      "replicate": args.ess_replicate},
            "detail": out}
     print(json.dumps(res), flush=True)
 
@@ -236,6 +238,8 @@ def main():
     ap.add_argument("--ess-warmup", type=int, default=300)
     ap.add_argument("--ess-burn", type=int, default=1000)
     ap.add_argument("--ess-iter", type=int, default=2000)
+    ap.add_argument("--ess-replicate", type=int, default=0,
+                    help="repeat the comparison with other random numbers (latent draws, chains, training)")
     ap.add_argument("--components", action="store_true",
                     help="only time the smaller steps (latent-location draw, surrogate inference and training)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",

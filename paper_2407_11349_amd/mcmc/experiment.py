@@ -209,7 +209,7 @@ def run_mh(target: HawkesCutTarget, z0, inv_mass, n_iter: int, it0: int, n_adapt
 
 
 def run_da_hmc(target: HawkesCutTarget, sur: Surrogate, hmc: HMC, z0, n_iter: int, it0: int, prior_var: float,
-               log=None) -> ChainResult:
+               log=None, seed=11) -> ChainResult:
     def sur_post(z):
         ll, g = sur.value_and_grad(z)
         return float(ll[0]) - 0.5 * float(np.dot(z, z)) / prior_var, g[0] - np.asarray(z) / prior_var
@@ -218,7 +218,7 @@ def run_da_hmc(target: HawkesCutTarget, sur: Surrogate, hmc: HMC, z0, n_iter: in
         return sur.leapfrog(z, p, grad, eps, inv_mass, n, prior_var)
 
     da = DelayedAcceptanceHMC(target, sur_post, n_leapfrog=hmc.n_leapfrog, step_size=hmc.eps,
-                              inv_mass=hmc.inv_mass, rng=np.random.default_rng(11),
+                              inv_mass=hmc.inv_mass, rng=np.random.default_rng(seed),
                               trajectory=trajectory if hasattr(sur, "leapfrog") else None)
     n0, g0 = target.n_loglik, target.n_grad
     _sync()
@@ -238,12 +238,16 @@ def run_da_hmc(target: HawkesCutTarget, sur: Surrogate, hmc: HMC, z0, n_iter: in
 
 
 def compare(events, county, rect, *, n_burn=1000, n_iter=2000, n_leapfrog=20, seed=2002, lam=1.0, epochs=60,
-            n_warmup=300, log=None) -> dict:
+            n_warmup=300, log=None, replicate: int = 0) -> dict:
+    """The sampler comparison on one event set.  `replicate` r > 0 repeats it with other random numbers
+    throughout: latent-location draws (Philox seed + 100 r), warm-up and burn-in, surrogate training and the
+    three samplers."""
     from synth.mlp_init import init_params
 
-    target = HawkesCutTarget(events, county, rect, seed=seed, precision="fp32_skip")
+    r = int(replicate)
+    target = HawkesCutTarget(events, county, rect, seed=seed + 100 * r, precision="fp32_skip")
     z0 = np.log(np.array([0.5, 10.0, 7.0, 0.3, 2.0, 0.2]))
-    hmc, st, rec, t_burn = burn_in(target, z0, n_burn, n_leapfrog, seed=1, n_warmup=n_warmup, log=log)
+    hmc, st, rec, t_burn = burn_in(target, z0, n_burn, n_leapfrog, seed=1 + r, n_warmup=n_warmup, log=log)
     Zt, Lt, Gt, Ht = np.array(rec.z), np.array(rec.ll), np.array(rec.g), np.array(rec.grp, dtype=np.int64)
     n = Zt.shape[0]
     # hold out whole latent-location draws (10%); the value fit is up to one offset per draw
@@ -257,7 +261,7 @@ def compare(events, county, rect, *, n_burn=1000, n_iter=2000, n_leapfrog=20, se
     std = Standardiser.fit(Zt[tr], Lt[tr], remap[Ht[tr]])
     t0 = time.time()
     net = SurrogateNet(init_params(3))
-    hist = train(net, std, Zt[tr], Lt[tr], Gt[tr], lam=lam, epochs=epochs, batch=256, lr=1e-3, seed=5, log=log,
+    hist = train(net, std, Zt[tr], Lt[tr], Gt[tr], lam=lam, epochs=epochs, batch=256, lr=1e-3, seed=5 + r, log=log,
                  groups=remap[Ht[tr]])
     _sync()
     t_train = time.time() - t0
@@ -279,9 +283,9 @@ def compare(events, county, rect, *, n_burn=1000, n_iter=2000, n_leapfrog=20, se
         log(f"surrogate: {held}")
     it0 = n_warmup + n_burn + 1
     plain = run_plain_hmc(target, hmc, st.z, n_iter, it0, log=log)
-    dah = run_da_hmc(target, sur, hmc, st.z, n_iter, it0 + n_iter + 1, target.prior_var, log=log)
-    mh = run_mh(target, st.z, hmc.inv_mass, n_iter, it0 + 2 * n_iter + 2, log=log)
-    out = {"burn_in_seconds": t_burn, "surrogate": held, "step_size": hmc.eps, "n_iter": n_iter}
+    dah = run_da_hmc(target, sur, hmc, st.z, n_iter, it0 + n_iter + 1, target.prior_var, log=log, seed=11 + r)
+    mh = run_mh(target, st.z, hmc.inv_mass, n_iter, it0 + 2 * n_iter + 2, log=log, seed=13 + r)
+    out = {"burn_in_seconds": t_burn, "surrogate": held, "step_size": hmc.eps, "n_iter": n_iter, "replicate": r}
     for name, r in (("plain_hmc", plain), ("da_hmc", dah), ("univariate_mh", mh)):
         s = _summary(r.draws)
         ess_min = float(np.min(s["bulk_ess"]))
