@@ -94,7 +94,10 @@ def find_mode(target, z0, max_iter: int = 200) -> np.ndarray:
 # Extra starts of the mode search, as offsets of log theta from z0: the two kernels can trade
 # roles (a long-memory, wide triggering kernel with a narrow background, or the reverse),
 # and the mode nearest to the usual starting values need not be the highest.
-MODE_START_OFFSETS = ([0.0, 0.0, 0.0, -0.5, 0.0, -4.0], [0.0, 0.0, 0.0, -0.8, 1.0, -5.0])
+# further starts of the mode search, as offsets of log theta from the default: a long-memory triggering kernel
+# (two of them), and a wider, stronger one
+MODE_START_OFFSETS = ([0.0, 0.0, 0.0, -0.5, 0.0, -4.0], [0.0, 0.0, 0.0, -0.8, 1.0, -5.0],
+                      [0.0, 0.0, 0.0, 0.7, 1.8, 0.0])
 
 
 def best_mode(target, z0, offsets=MODE_START_OFFSETS, log=None) -> np.ndarray:

@@ -124,7 +124,7 @@ def generate(k: str | WorkloadConfig, n: int | None = None, seed: int | None = N
 
 
 def generate_clustered(n: int = 100_000, seed: int = 1101, t_max: float = 1000.0, nx: int = 50, ny: int = 60,
-                       rho_sdlog: float = 1.0, branching: float = 0.6, delay_days: float = 5.0, h_km: float = 2.0,
+                       rho_sdlog: float = 1.0, branching: float = 0.6, delay_days: float = 5.0, h_km: float = 12.0,
                        n_waves: int = 6, wave_sd_days: float = 25.0, uniform_share: float = 0.3) -> EventSet:
     """A seeded branching (cluster) process over the workloads' box and county grid.
 
@@ -138,6 +138,13 @@ def generate_clustered(n: int = 100_000, seed: int = 1101, t_max: float = 1000.0
     ``Exp(mean delay_days)`` later and displaced by N(0, (h_km s)^2) per axis, s the
     bandwidth scale of the parent's county.  Cases after t_max are dropped and the set is
     thinned uniformly at random to exactly n events.
+
+    The displacement scale is chosen above the county cells' size (20 x 16.7 km on the
+    default grid): the cut posterior redraws every location uniformly within its county, so
+    offspring structure finer than a county is lost, and with h_km = 2 the triggering kernel
+    instead settled at county or hot-spot scale in two competing posterior modes of nearly
+    equal height.  At 12 km the mode near the generating scales is higher than any other by
+    about 100 nats or more under every latent draw tried.
     """
     cfg = WorkloadConfig(f"n{n // 1000}k_clustered_{int(t_max)}d_{nx * ny}c", n, t_max, nx, ny, rho_sdlog, seed)
     rng = np.random.default_rng(seed)
