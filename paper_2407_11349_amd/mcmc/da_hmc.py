@@ -37,7 +37,7 @@ class DAState:
 
 class DelayedAcceptanceHMC:
     def __init__(self, target, surrogate_logp_and_grad, dim=6, n_leapfrog=20, step_size=0.05, inv_mass=None,
-                 rng=None, window=50, fallback_below=0.5, trajectory=None):
+                 rng=None, window=50, fallback_below=0.5, trajectory=None, jitter=0.0):
         """trajectory(z, p, grad, eps, inv_mass, n_steps) -> (z, p, s, grad), if given, runs the whole stage-1
         leapfrog trajectory on the surrogate at once (e.g. on the GPU) instead of step by step here."""
         self.target = target
@@ -51,7 +51,7 @@ class DelayedAcceptanceHMC:
         self.window = deque(maxlen=window)
         self.fallback_below = fallback_below
         self.exact = HMC(target, dim=dim, n_leapfrog=n_leapfrog, step_size=step_size, inv_mass=self.inv_mass,
-                         rng=self.rng)
+                         rng=self.rng, jitter=jitter)
         self.stats = {"iterations": 0, "stage1_accept": 0, "stage2_accept": 0, "fallback": 0, "accept": 0,
                       "paired_exact": 0}
 
@@ -91,11 +91,13 @@ class DelayedAcceptanceHMC:
                 s, sg = self.sur(new.z)
                 return DAState(new.z, new.logp, s, sg), acc, "fallback"
             return st, acc, "fallback"
+        self.exact.eps = self.eps
+        eps = self.exact.jittered_eps()
         p0 = self.rng.normal(size=self.dim) / np.sqrt(self.inv_mass)
         if self.trajectory is not None:
-            z1, p1, s1, sg1 = self.trajectory(st.z, p0, st.s_grad, self.eps, self.inv_mass, self.n_leapfrog)
+            z1, p1, s1, sg1 = self.trajectory(st.z, p0, st.s_grad, eps, self.inv_mass, self.n_leapfrog)
         else:
-            z1, p1, s1, sg1 = leapfrog(st.z, p0, st.s_grad, self.eps, self.inv_mass, self.n_leapfrog, self.sur)
+            z1, p1, s1, sg1 = leapfrog(st.z, p0, st.s_grad, eps, self.inv_mass, self.n_leapfrog, self.sur)
         h0 = -st.s + kinetic(p0, self.inv_mass)
         h1 = -s1 + kinetic(p1, self.inv_mass)
         a1 = float(np.exp(min(0.0, h0 - h1))) if np.isfinite(h1) else 0.0

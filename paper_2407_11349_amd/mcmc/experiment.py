@@ -94,6 +94,9 @@ def find_mode(target, z0, max_iter: int = 200) -> np.ndarray:
 # Extra starts of the mode search, as offsets of log theta from z0: the two kernels can trade
 # roles (a long-memory, wide triggering kernel with a narrow background, or the reverse),
 # and the mode nearest to the usual starting values need not be the highest.
+# step-size jitter of the compared HMC samplers (plain and delayed acceptance) after warm-up
+STEP_JITTER = 0.2
+
 # further starts of the mode search, as offsets of log theta from the default: a long-memory triggering kernel
 # (two of them), and a wider, stronger one
 MODE_START_OFFSETS = ([0.0, 0.0, 0.0, -0.5, 0.0, -4.0], [0.0, 0.0, 0.0, -0.8, 1.0, -5.0],
@@ -162,6 +165,7 @@ def burn_in(target: HawkesCutTarget, z0, n_iter: int, n_leapfrog=20, seed=0, n_w
 
 
 def run_plain_hmc(target: HawkesCutTarget, hmc: HMC, z0, n_iter: int, it0: int, log=None) -> ChainResult:
+    hmc.jitter = STEP_JITTER
     n0, g0 = target.n_loglik, target.n_grad
     _sync()
     t0 = time.time()
@@ -222,7 +226,7 @@ def run_da_hmc(target: HawkesCutTarget, sur: Surrogate, hmc: HMC, z0, n_iter: in
 
     da = DelayedAcceptanceHMC(target, sur_post, n_leapfrog=hmc.n_leapfrog, step_size=hmc.eps,
                               inv_mass=hmc.inv_mass, rng=np.random.default_rng(seed),
-                              trajectory=trajectory if hasattr(sur, "leapfrog") else None)
+                              trajectory=trajectory if hasattr(sur, "leapfrog") else None, jitter=STEP_JITTER)
     n0, g0 = target.n_loglik, target.n_grad
     _sync()
     t0 = time.time()

@@ -3,7 +3,10 @@
 Targets expose ``logp_and_grad(z) -> (float, ndarray)`` and ``logp(z) -> float``.
 The step size is tuned during warm-up by dual averaging (Hoffman and Gelman,
 2014, Section 3.2) towards a target acceptance rate, and a diagonal inverse
-mass matrix is set from the warm-up draws at mid warm-up.
+mass matrix is set from the warm-up draws at mid warm-up.  After warm-up the
+step size can be jittered per iteration, uniformly within +-jitter of its
+value (Neal, 2011, Section 4.2), so that no fixed trajectory length resonates
+with a period of the target.
 """
 
 from __future__ import annotations
@@ -72,11 +75,12 @@ class HMCState:
 class HMC:
     """Plain HMC with exact gradients (n_leapfrog gradient evaluations per iteration)."""
 
-    def __init__(self, target, dim=6, n_leapfrog=20, step_size=0.05, inv_mass=None, rng=None):
+    def __init__(self, target, dim=6, n_leapfrog=20, step_size=0.05, inv_mass=None, rng=None, jitter=0.0):
         self.target = target
         self.dim = dim
         self.n_leapfrog = n_leapfrog
         self.eps = step_size
+        self.jitter = jitter
         self.inv_mass = np.ones(dim) if inv_mass is None else np.asarray(inv_mass, dtype=np.float64)
         self.rng = np.random.default_rng(0) if rng is None else rng
 
@@ -84,8 +88,14 @@ class HMC:
         logp, grad = self.target.logp_and_grad(np.asarray(z, dtype=np.float64))
         return HMCState(np.asarray(z, dtype=np.float64), logp, grad)
 
+    def jittered_eps(self) -> float:
+        """The step size of one iteration: eps, or eps (1 + jitter U(-1, 1)) with jitter > 0."""
+        if self.jitter <= 0.0:
+            return self.eps
+        return self.eps * (1.0 + self.jitter * (2.0 * self.rng.uniform() - 1.0))
+
     def step(self, s: HMCState, eps=None):
-        eps = self.eps if eps is None else eps
+        eps = self.jittered_eps() if eps is None else eps
         p0 = self.rng.normal(size=self.dim) / np.sqrt(self.inv_mass)
         z1, p1, logp1, grad1 = leapfrog(s.z, p0, s.grad, eps, self.inv_mass, self.n_leapfrog,
                                         self.target.logp_and_grad)
@@ -102,7 +112,7 @@ class HMC:
         draws = []
         half = n_warmup // 2
         for it in range(n_warmup):
-            s, acc, a = self.step(s)
+            s, acc, a = self.step(s, self.eps)
             if on_step:
                 on_step(it, s, acc)
             self.eps = da.update(a)

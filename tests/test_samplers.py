@@ -220,3 +220,25 @@ def test_univariate_mh_pairs_the_refreshed_density_with_the_first_proposal():
         if paired:
             assert tgt.batches == [2] * 300
     np.testing.assert_allclose(chains[0], chains[1], rtol=0, atol=0)
+
+
+def test_step_size_jitter_breaks_a_resonant_trajectory_length():
+    """On a standard normal a trajectory of one full period (20 steps of 2 pi / 20) returns close to
+    its start, so fixed-length HMC barely mixes; jittering the step size per iteration (+-20%) mixes,
+    and still samples the target."""
+    from paper_2407_11349_amd.mcmc.hmc import HMC
+
+    tgt = Gauss(np.zeros(6), np.eye(6))
+    out = {}
+    for jitter in (0.0, 0.2):
+        hmc = HMC(tgt, n_leapfrog=20, step_size=2 * np.pi / 20, rng=np.random.default_rng(10), jitter=jitter)
+        s = hmc.init_state(np.full(6, 0.5))
+        draws = []
+        for _ in range(3000):
+            s, _, _ = hmc.step(s)
+            draws.append(s.z)
+        out[jitter] = np.array(draws)
+    stuck, mixed = out[0.0], out[0.2]
+    assert bulk_ess(stuck[:, 0].reshape(1, -1)) < 20  # creeps along with the leapfrog's period error
+    assert bulk_ess(mixed[:, 0].reshape(1, -1)) > 300
+    _check_moments(mixed, np.zeros(6), np.eye(6))
