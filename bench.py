@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "loglik+grad pairs/s at N=1M, FP32 vs FP64; ESS/s surrogate-HMC vs plain HMC"
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector: 256 CU x 2.4 GHz x 256 FLOP/clk
+PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector
 # v_exp_f32 issue rate measured on the box (31.9 lane-ops/clk/CU, profiles/valu_rates_gfx950.md)
 EXP_PEAK_PER_S = 1.958e13
 # algorithmic FLOP per pair of the fused sweep (FMA = 2, add/sub/mul = 1; exp counted apart):
@@ -355,7 +356,11 @@ def main():
         torch.cuda.synchronize()
         d64 = time.perf_counter() - t1
         result["fp64"] = {"value": pairs / d64, "unit": "pairs/s", "ms_per_eval": d64 * 1e3,
-                          "fp32_speedup": (pairs / (ms_step / 1e3)) / (pairs / d64)}
+                          "fp32_speedup": (pairs / (ms_step / 1e3)) / (pairs / d64),
+                          "achieved_tflops": flop_per_launch / d64 / 1e12,
+                          "frac_of_fp64_peak": flop_per_launch / d64 / 1e12 / PEAK_FP64_TFLOPS,
+                          "note": "same fixed algorithmic FLOP count as the FP32 roofline (exponentials "
+                                  "counted apart; each is ~17 FP64 operations here)"}
         log(f"fp64 evaluation: {d64 * 1e3:.1f} ms")
         del ws64
 
