@@ -1,0 +1,75 @@
+"""GPU checks at 4e6 events (the 1200-day workload four times as dense; 46 GB of FP32 workspace): sizes
+where offsets into the partial-sum region pass 2^31 elements' worth of bytes and the symmetric sweep runs
+25,600 workgroups.  The full FP64 oracle value is out of reach here (~14 h of CPU), so the checks are
+per-event rates of sampled rows against the oracle, additivity over row ranges (row sweep against the
+symmetric sweep), the skip mode against the full sweep, and bitwise reproducibility."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+import paper_2407_11349_amd as hk
+
+pytestmark = pytest.mark.gpu
+
+N = 4_000_000
+TOL_EV = 5e-6
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def big():
+    ev = synth.generate(synth.N1M, n=N, seed=77)
+    dev = hk.DeviceEvents.from_arrays(ev.t, ev.x, ev.y, ev.s)
+    ws = hk.Workspace(N, "fp32")
+    yield ev, dev, ws
+    del ws
+    torch.cuda.empty_cache()
+
+
+def test_large_sampled_rows_against_oracle(big):
+    ev, dev, ws = big
+    th = synth.theta_default()
+    rng = np.random.default_rng(8)
+    starts = np.sort(rng.choice(N - 4, 24, replace=False))
+    for a in starts:
+        a = int(a)
+        lam_ref = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th, rows=(a, a + 4), per_row=True)[2]
+        lam, _ = hk.event_terms(dev, th, precision="fp32", rows=(a, a + 4), ws=ws)
+        np.testing.assert_allclose(lam.cpu().numpy(), lam_ref, rtol=TOL_EV)
+    _say(f"n4m: 24 x 4 sampled rows within {TOL_EV} of the oracle")
+
+
+def test_large_symmetric_equals_row_ranges_and_is_reproducible(big):
+    _, dev, ws = big
+    th = synth.theta_default()
+    ll, g = hk.loglik_grad(dev, th, precision="fp32", ws=ws)
+    torch.cuda.synchronize()
+    ll, g = float(ll.item()), g.cpu().numpy()
+    assert np.isfinite(ll) and np.all(np.isfinite(g))
+    ll2, g2 = hk.loglik_grad(dev, th, precision="fp32", ws=ws)
+    assert float(ll2.item()) == ll and np.array_equal(g2.cpu().numpy(), g)
+    cut = 2_600_001
+    parts = [hk.loglik_grad(dev, th, precision="fp32", rows=r, ws=ws) for r in ((0, cut), (cut, N))]
+    lr = sum(float(p[0].item()) for p in parts)
+    gr = sum(p[1].cpu().numpy() for p in parts)
+    _say(f"n4m: loglik {ll:.6f}, row ranges {lr:.6f} (rel {abs(lr - ll) / abs(ll):.2e})")
+    assert abs(lr - ll) <= 1e-9 * abs(ll)
+    np.testing.assert_allclose(gr, g, rtol=1e-6)
+
+
+def test_large_skip_mode_equals_full_sweep(big):
+    _, dev, ws = big
+    th = synth.theta_default()
+    full = hk.loglik_grad(dev, th, precision="fp32", ws=ws)
+    full = float(full[0].item()), full[1].cpu().numpy()
+    skip = hk.loglik_grad(dev, th, precision="fp32_skip", ws=ws)
+    skip = float(skip[0].item()), skip[1].cpu().numpy()
+    _say(f"n4m: skip vs full loglik rel {abs(skip[0] - full[0]) / abs(full[0]):.2e}")
+    assert abs(skip[0] - full[0]) <= 1e-13 * abs(full[0])
+    np.testing.assert_allclose(skip[1], full[1], rtol=1e-10)
