@@ -201,6 +201,46 @@ def component_timings(hk, torch, county, rect, x, y) -> dict:
     return out
 
 
+def sampler_costs(args, hk, synth, torch):
+    """Per-call costs of the samplers' exact steps on the clustered workload at another size (no chains): the
+    latent-location draw, one loglik+gradient (plain HMC: 21 per iteration), one two-vector loglik (the
+    delayed-acceptance correction) and a 20-step surrogate trajectory, at the posterior scales of the 1e5 runs."""
+    from paper_2407_11349_amd.surrogate import SurrogateNet, Standardiser, Surrogate
+    from synth.mlp_init import init_params
+
+    ev = synth.generate_clustered(n=args.sampler_costs)
+    dev = hk.DeviceEvents.from_arrays(ev.t, ev.x, ev.y, ev.s, device="cuda")
+    county = torch.from_numpy(ev.county).cuda()
+    rect = torch.from_numpy(ev.rect).cuda()
+    th = np.exp(np.array([-0.198, 2.535, 2.421, -1.709, 2.550, -1.082]))  # posterior means at 1e5 events
+    th2 = np.stack([th, th * np.array([1.01, 0.99, 1.01, 0.99, 1.01, 0.99])])
+    ws = hk.Workspace(ev.n, "fp32_skip")
+    it = [0]
+
+    def draw():
+        it[0] += 1
+        hk.resample_locations(county, rect, 2002, it[0], dev.x, dev.y)
+
+    grad = event_ms(torch, lambda: hk.loglik_grad(dev, th, precision="fp32_skip", ws=ws), 3)
+    pair = event_ms(torch, lambda: hk.loglik_batch(dev, th2, precision="fp32_skip", ws=ws), 3)
+    one = event_ms(torch, lambda: hk.loglik(dev, th, precision="fp32_skip", ws=ws), 3)
+    rs = event_ms(torch, draw, 10)
+    std = Standardiser(m_z=np.log(th), s_z=np.full(6, 0.03), m_y=0.0, s_y=4.0)
+    sur = Surrogate(SurrogateNet(init_params(3)), std)
+    z0 = np.log(th)
+    t0 = time.perf_counter()
+    for _ in range(20):
+        sur.leapfrog(z0, np.zeros(6), np.zeros(6), 0.25, np.full(6, 1e-3), 20, 100.0)
+    traj = (time.perf_counter() - t0) / 20 * 1e3
+    res = {"workload": ev.config.name, "n_events": ev.n, "precision": "fp32_skip",
+           "ms_loglik_grad": grad, "ms_loglik_pair": pair, "ms_loglik": one, "ms_resample": rs,
+           "ms_surrogate_trajectory_20_steps_host_round_trip": traj,
+           "ms_plain_hmc_iteration": 21 * grad + rs,
+           "note": "kernel time of each call (HIP events on the library's stream); the trajectory includes its "
+                   "host round trip"}
+    print(json.dumps(res), flush=True)
+
+
 def run_ess(args, hk, synth, torch):
     """ESS/s of delayed-acceptance HMC with the BF16 surrogate against plain exact-gradient HMC, both on the
     cut posterior (X redrawn every iteration) with the FP32 GPU likelihood, 20 leapfrog steps."""
@@ -243,6 +283,8 @@ def main():
                     help="repeat the comparison with other random numbers (latent draws, chains, training)")
     ap.add_argument("--components", action="store_true",
                     help="only time the smaller steps (latent-location draw, surrogate inference and training)")
+    ap.add_argument("--sampler-costs", type=int, default=0, metavar="N",
+                    help="only time the samplers' exact steps on the clustered workload with N events")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES device-to-device (scales the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -267,6 +309,9 @@ def main():
 
     if args.ess:
         run_ess(args, hk, synth, torch)
+        return
+    if args.sampler_costs:
+        sampler_costs(args, hk, synth, torch)
         return
 
     cfg = synth.N1M
