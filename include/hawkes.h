@@ -104,8 +104,8 @@ enum hawkes_status {
 
 /* Bytes of workspace the likelihood calls need for n events at `precision`
  * (0 if the arguments are invalid).  FP64: linear in n.  FP32: the symmetric
- * sweep keeps 9 doubles per event for each of up to 160 event groups (about
- * 11.5 GB at n = 10^6), so the size grows with n as n * min(n / 512, 160). */
+ * sweep keeps 9 doubles per event for each of up to 384 event groups (about
+ * 24 GB at n = 10^6), so the size grows with n as n * min(n / 512, 384). */
 size_t hawkes_workspace_bytes(int64_t n, int precision);
 
 /* Log-likelihood of rows [row_begin, row_end):  *d_loglik = sum_n l_n
@@ -187,7 +187,7 @@ int hawkes_tune_target_workgroups(int64_t wgs);
 /* Tuning: the symmetric FP32 sweep over the whole event set splits the
  * events into about `groups` row groups and as many column groups (one
  * workgroup per pair of groups it needs, about groups^2 / 2);
- * 0 <= groups <= 160, default 160; 0 makes whole-set calls take the row
+ * 0 <= groups <= 384, default 384; 0 makes whole-set calls take the row
  * sweep too.  Results do not depend on it beyond FP64 summation order of the
  * partial sums (0 changes the order of the FP32 background sums as well).
  * Process-wide setting. */

@@ -37,6 +37,8 @@ EXPORTS = (
 )
 # hawkes_mlp_leapfrog_io: 42 doubles (z, p, grad, inv_mass, m_z, s_z: 6 each; m_y, s_y, prior_var, eps, s, status)
 LEAPFROG_IO_DOUBLES = 42
+# default (and largest) group count of the symmetric FP32 sweep (hawkes_tune_symmetric_groups)
+SYM_GROUPS_DEFAULT = 384
 MLP_PARAMS = 133633
 
 

@@ -102,7 +102,10 @@ constexpr int KT = HAWKES_KT;             // target rows per lane
 constexpr int TB = WG * KT;               // target rows per workgroup
 constexpr int GS = HAWKES_GS;             // FP32 terms summed before folding into FP64
 constexpr int64_t MAX_TARGET_WGS = 65536; // upper bound used for workspace sizing
-constexpr int MAX_SYM_GROUPS = 160;       // row / column groups of the symmetric sweep (workspace bound)
+// row / column groups of the symmetric sweep (workspace bound): 384 splits
+// 10^6 events into 326 x 326 groups of 6 blocks, whose ~53,000 workgroups
+// leave a shorter tail than 160 groups (151 x 151 of 13 blocks) did
+constexpr int MAX_SYM_GROUPS = 384;
 constexpr int MAX_FUSED_THETA = 2;        // parameter vectors one batched sweep evaluates together
 constexpr int64_t MAX_N = int64_t(1) << 30;
 constexpr double LOG2E = 1.4426950408889634074;
@@ -164,7 +167,7 @@ SymPlan make_sym_plan(int64_t num_tb, int64_t num_tiles, int groups)
     return S;
 }
 
-int g_sym_groups = 160;
+int g_sym_groups = MAX_SYM_GROUPS;
 
 // Per-source FP32 record fields in 8-byte slots (pairs), so that one index
 // scale addresses every field of a source in LDS.

@@ -38,7 +38,7 @@ SHAPES = {
 }
 
 # how whole-set FP32 calls are swept: ("sym", groups) or ("rows", target workgroups)
-MODES = [("sym", 96), ("sym", 128), ("sym", 160), ("rows", 32768)]
+MODES = [("sym", 160), ("sym", 200), ("sym", 256), ("sym", 320), ("sym", 384), ("rows", 32768)]
 
 
 def _build_one(name: str) -> str:
@@ -121,7 +121,7 @@ def time_shapes(names, n: int) -> None:
         del ws
         hk.set_timing(False)
         lib.hawkes_tune_target_workgroups(32768)
-        lib.hawkes_tune_symmetric_groups(160)
+        lib.hawkes_tune_symmetric_groups(_lib.SYM_GROUPS_DEFAULT)
 
 
 def main() -> None:

@@ -237,7 +237,7 @@ def test_chunking_does_not_change_results_beyond_rounding(prec):
             vals.append(_gpu_ll_grad(dev, th, prec))
     finally:
         lib.hawkes_tune_target_workgroups(32768)
-        lib.hawkes_tune_symmetric_groups(160)
+        lib.hawkes_tune_symmetric_groups(_lib.SYM_GROUPS_DEFAULT)
     for ll, g in vals[1:]:
         assert ll == pytest.approx(vals[0][0], rel=1e-11)
         np.testing.assert_allclose(g, vals[0][1], rtol=1e-8)

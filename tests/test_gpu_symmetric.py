@@ -18,7 +18,7 @@ from paper_2407_11349_amd import _lib
 pytestmark = pytest.mark.gpu
 
 TOL_L, TOL_G, TOL_EV = 1e-9, 1e-6, 5e-6
-DEFAULT_GROUPS = 160
+DEFAULT_GROUPS = _lib.SYM_GROUPS_DEFAULT
 
 
 def _say(msg):
@@ -76,7 +76,7 @@ def test_symmetric_against_oracle_and_row_sweep(kind):
     np.testing.assert_allclose(sym[2], row[2], rtol=1e-6)
 
 
-@pytest.mark.parametrize("groups", [1, 2, 3, 5, 41, 160])
+@pytest.mark.parametrize("groups", [1, 2, 3, 5, 41, 160, 384])
 def test_group_counts_change_only_fp64_order(groups):
     t, ev = _events("days", 9000, 3)
     th = synth.theta_default()
