@@ -760,8 +760,11 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
 
             if (cls != MIXED) {
                 const bool causal = (cls == CAUSAL);
-                // column sums (CAUSAL with columns): FP32 over 8 rotation steps, then FP64
-                float e0 = 0.0f, e1 = 0.0f, e2 = 0.0f;
+                // column sums (CAUSAL with columns): FP32 over 8 rotation steps, then FP64.
+                // FP32 sums start at -0, the exact additive identity (x + -0 = x for every
+                // x, +0 included), so the compiler can drop a sum's first addition and turn
+                // fma(a, b, -0) into a product; a +0 start would cost an instruction
+                float e0 = -0.0f, e1 = -0.0f, e2 = -0.0f;
                 double h0 = 0.0, h1 = 0.0, h2 = 0.0;
                 for (int m0 = 0; m0 < TS; m0 += GS) {
                     float f[KT][6];
@@ -769,7 +772,7 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
                     for (int q = 0; q < KT; ++q)
 #pragma unroll
                         for (int z = 0; z < 6; ++z)
-                            f[q][z] = 0.0f;
+                            f[q][z] = -0.0f;
                     // background + triggering terms of one source for the lane's targets;
                     // adds the background terms' sums over those targets (b, b D, b A) to c0..c2
                     auto causal_pair = [&](int m, float &c0, float &c1, float &c2) {
@@ -832,7 +835,7 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
                         // takes source sub + ((i + step) mod 16) at step step of the subgroup
                         HK_UNROLL(UJ)
                         for (int j = 0; j < GS; ++j) {
-                            float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+                            float c0 = -0.0f, c1 = -0.0f, c2 = -0.0f;
                             causal_pair(sub + ((li + s0 + j) & 15), c0, c1, c2);
                             e0 = row_rotate_f32(e0) + c0;
                             if (GRAD) {
@@ -865,11 +868,11 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
                                 }
                             }
                         }
-                        e0 = e1 = e2 = 0.0f;
+                        e0 = e1 = e2 = -0.0f;
                     } else if (causal) {
                         HK_UNROLL(UJ)
                         for (int j = 0; j < GS; ++j) {
-                            float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+                            float c0 = -0.0f, c1 = -0.0f, c2 = -0.0f;
                             causal_pair(m0 + j, c0, c1, c2);  // column sums unused
                         }
                     } else {
@@ -936,7 +939,7 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
                     for (int q = 0; q < KT; ++q)
 #pragma unroll
                         for (int z = 0; z < 6; ++z)
-                            f[q][z] = 0.0f;
+                            f[q][z] = -0.0f;
                     for (int j = 0; j < GS; ++j) {
                         const int m = m0 + j;
                         const double xm = sx[m], ym = sy[m], tm = st[m];
@@ -1248,7 +1251,7 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32_batch(PairBatchF32
                 double h[NT];
 #pragma unroll
                 for (int z = 0; z < NT; ++z) {
-                    e[z] = 0.0f;
+                    e[z] = -0.0f;
                     h[z] = 0.0;
                 }
                 for (int m0 = 0; m0 < TS; m0 += GS) {
@@ -1257,7 +1260,7 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32_batch(PairBatchF32
                     for (int q = 0; q < KT; ++q)
 #pragma unroll
                         for (int z = 0; z < NT; ++z)
-                            f[q][z][0] = f[q][z][1] = 0.0f;
+                            f[q][z][0] = f[q][z][1] = -0.0f;
                     // background + triggering terms of source m for the lane's targets;
                     // adds each vector's background terms over those targets to c[z]
                     auto causal_pair = [&](int m, float (&c)[NT]) {
@@ -1306,7 +1309,7 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32_batch(PairBatchF32
                             float c[NT];
 #pragma unroll
                             for (int z = 0; z < NT; ++z)
-                                c[z] = 0.0f;
+                                c[z] = -0.0f;
                             causal_pair(sub + ((li + s0 + j) & 15), c);
 #pragma unroll
                             for (int z = 0; z < NT; ++z)
@@ -1330,14 +1333,14 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32_batch(PairBatchF32
                         }
 #pragma unroll
                         for (int z = 0; z < NT; ++z)
-                            e[z] = 0.0f;
+                            e[z] = -0.0f;
                     } else if (causal) {
                         HK_UNROLL(HAWKES_UJ)
                         for (int j = 0; j < GS; ++j) {
                             float c[NT];
 #pragma unroll
                             for (int z = 0; z < NT; ++z)
-                                c[z] = 0.0f;
+                                c[z] = -0.0f;
                             causal_pair(m0 + j, c);  // column sums unused
                         }
                     } else {
@@ -1383,7 +1386,7 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32_batch(PairBatchF32
                     for (int q = 0; q < KT; ++q)
 #pragma unroll
                         for (int z = 0; z < NT; ++z)
-                            f[q][z][0] = f[q][z][1] = 0.0f;
+                            f[q][z][0] = f[q][z][1] = -0.0f;
                     for (int j = 0; j < GS; ++j) {
                         const int m = m0 + j;
                         const double xm = T.x[m], ym = T.y[m], tm = T.t[m];
@@ -1716,7 +1719,7 @@ __global__ __launch_bounds__(WG) void k_pair_f64(PairF64 a)
                 for (int m0 = 0; m0 < TS; m0 += 16) {
                     double e0 = 0.0, e1 = 0.0, e2 = 0.0;
                     for (int j = 0; j < 16; ++j) {
-                        double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+                        double c0 = -0.0, c1 = -0.0, c2 = -0.0;  // -0: first addition folds away
                         pair(m0 + ((li + j) & 15), true, c0, c1, c2);
                         e0 = row_rotate_f64(e0) + c0;
                         if (GRAD) {
@@ -1742,7 +1745,7 @@ __global__ __launch_bounds__(WG) void k_pair_f64(PairF64 a)
             } else {
                 const int mlen = (k * TS + TS <= a.n) ? TS : a.n - k * TS;
                 for (int m = 0; m < mlen; ++m) {
-                    double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+                    double c0 = -0.0, c1 = -0.0, c2 = -0.0;  // -0: first addition folds away
                     pair(m, cls != MIXED, c0, c1, c2);  // column sums unused
                 }
             }

@@ -32,6 +32,7 @@ SHAPES = {
     "kt2": {"HAWKES_KT": 2},
     "kt2_uj1": {"HAWKES_KT": 2, "HAWKES_UJ_GRAD": 1},
     "kt2_uj2": {"HAWKES_KT": 2, "HAWKES_UJ_GRAD": 2},
+    "kt2_uj8": {"HAWKES_KT": 2, "HAWKES_UJ_GRAD": 8},
     "kt2_w3": {"HAWKES_KT": 2, "HAWKES_WAVES_PER_EU": 3},
     "kt1": {"HAWKES_KT": 1},
     "kt4": {"HAWKES_KT": 4},
