@@ -94,7 +94,9 @@ def test_host_validation_paths(lib):
     assert lib.hawkes_tune_target_workgroups(0) == -1
     assert lib.hawkes_tune_target_workgroups(10**6) == -1
     assert lib.hawkes_tune_symmetric_groups(-1) == -1
-    assert lib.hawkes_tune_symmetric_groups(385) == -1
+    assert lib.hawkes_tune_symmetric_groups(_lib.SYM_GROUPS_DEFAULT + 1) == -1
+    # the binding's default is the library's largest accepted group count
+    assert lib.hawkes_tune_symmetric_groups(_lib.SYM_GROUPS_DEFAULT) == 0
     assert lib.hawkes_last_pair_kernel_ms(None) == -1
 
 
