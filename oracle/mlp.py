@@ -12,10 +12,9 @@ out x in), b1, W2 (256x256), b2, W3 (256x256), b3, w4 (256), b4 (1):
 copies; the functions here take whatever weights they are given (the tests
 pass the BF16-rounded ones) and compute in FP64.
 
-The parameter gradient of the gradient-matching term uses the identity
-d/dtheta [r . grad_z f] = d/dtheta [D_r f] for a fixed vector r: the
-directional derivative D_r f is a forward-mode tangent pass, and one reverse
-pass through the primal and tangent computations gives both terms.
+The parameter gradient is the chain rule of the loss written out: reverse
+mode through the primal pass and through the reverse pass that forms
+grad_z f (reverse over reverse).
 """
 
 from __future__ import annotations
@@ -96,59 +95,72 @@ def forward(theta, z):
 
 
 def sobolev_loss_and_grad(theta, z, y, g, lam):
-    """Loss (scalar) and its gradient with respect to the flat parameter vector."""
+    """Loss (scalar) and its gradient with respect to the flat parameter vector.
+
+    The loss reads the network twice: its value f and its input gradient
+    grad_z f, which is itself a computation (the reverse pass below).  The
+    parameter gradient is the chain rule applied to that whole graph: first
+    the adjoints of the reverse pass (from the gradient-matching term), then
+    the adjoints of the primal pass, which receive contributions both from f
+    and from the activation slopes s_k = GELU'(h_k) that the reverse pass read
+    (their derivative brings in GELU'')."""
     p = unpack(theta)
     z = np.atleast_2d(np.asarray(z, dtype=np.float64))
     y = np.asarray(y, dtype=np.float64)
     g = np.atleast_2d(np.asarray(g, dtype=np.float64))
     B = z.shape[0]
+    W1, W2, W3, w4 = p["W1"], p["W2"], p["W3"], p["w4"]
     # primal pass
-    h1 = z @ p["W1"].T + p["b1"]
+    h1 = z @ W1.T + p["b1"]
     a1, s1 = gelu(h1), gelu_d1(h1)
-    h2 = a1 @ p["W2"].T + p["b2"]
+    h2 = a1 @ W2.T + p["b2"]
     a2, s2 = gelu(h2), gelu_d1(h2)
-    h3 = a2 @ p["W3"].T + p["b3"]
+    h3 = a2 @ W3.T + p["b3"]
     a3, s3 = gelu(h3), gelu_d1(h3)
-    f = a3 @ p["w4"] + p["b4"][0]
-    # input gradient (reverse mode)
-    d3 = p["w4"] * s3
-    d2 = (d3 @ p["W3"]) * s2
-    d1 = (d2 @ p["W2"]) * s1
-    gz = d1 @ p["W1"]
+    f = a3 @ w4 + p["b4"][0]
+    # reverse pass for grad_z f, with its intermediate values named
+    d3 = w4 * s3            # df/dh3
+    c2 = d3 @ W3            # df/da2
+    d2 = c2 * s2            # df/dh2
+    c1 = d2 @ W2            # df/da1
+    d1 = c1 * s1            # df/dh1
+    gz = d1 @ W1            # df/dz
     e = f - y
     r = gz - g
     loss = float(np.mean(e * e + lam * np.sum(r * r, axis=1)))
-    # tangent pass along r: the directional derivative D_r f
-    t1 = r @ p["W1"].T
-    u1 = s1 * t1
-    t2 = u1 @ p["W2"].T
-    u2 = s2 * t2
-    t3 = u2 @ p["W3"].T
-    u3 = s3 * t3
-    # reverse pass of J = cf * f + ct * D_r f, with cf, ct, r held constant
-    cf = (2.0 / B) * e
-    ct = (2.0 * lam / B)
+
+    # adjoints (x_bar = dL/dx), starting from the two outputs the loss reads
+    f_bar = (2.0 / B) * e
+    gz_bar = (2.0 * lam / B) * r
     grad = {}
-    grad["w4"] = cf @ a3 + ct * u3.sum(axis=0)
-    grad["b4"] = np.array([cf.sum()])
-    a3b = np.outer(cf, p["w4"])               # adjoint of a3
-    u3b = np.full_like(u3, ct) * p["w4"]      # adjoint of u3
-    t3b = u3b * s3
-    h3b = a3b * s3 + u3b * gelu_d2(h3) * t3
-    grad["W3"] = h3b.T @ a2 + t3b.T @ u2
-    grad["b3"] = h3b.sum(axis=0)
-    a2b = h3b @ p["W3"]
-    u2b = t3b @ p["W3"]
-    t2b = u2b * s2
-    h2b = a2b * s2 + u2b * gelu_d2(h2) * t2
-    grad["W2"] = h2b.T @ a1 + t2b.T @ u1
-    grad["b2"] = h2b.sum(axis=0)
-    a1b = h2b @ p["W2"]
-    u1b = t2b @ p["W2"]
-    t1b = u1b * s1
-    h1b = a1b * s1 + u1b * gelu_d2(h1) * t1
-    grad["W1"] = h1b.T @ z + t1b.T @ r
-    grad["b1"] = h1b.sum(axis=0)
+    # through the reverse pass, last operation first
+    grad["W1"] = d1.T @ gz_bar                  # gz = d1 W1
+    d1_bar = gz_bar @ W1.T
+    c1_bar = d1_bar * s1                        # d1 = c1 * s1
+    s1_bar = d1_bar * c1
+    grad["W2"] = d2.T @ c1_bar                  # c1 = d2 W2
+    d2_bar = c1_bar @ W2.T
+    c2_bar = d2_bar * s2                        # d2 = c2 * s2
+    s2_bar = d2_bar * c2
+    grad["W3"] = d3.T @ c2_bar                  # c2 = d3 W3
+    d3_bar = c2_bar @ W3.T
+    grad["w4"] = np.sum(d3_bar * s3, axis=0)    # d3 = w4 * s3
+    s3_bar = d3_bar * w4
+    # through the primal pass; each h_k feeds a_k = GELU(h_k) and s_k = GELU'(h_k)
+    grad["w4"] = grad["w4"] + f_bar @ a3        # f = a3 . w4 + b4
+    grad["b4"] = np.array([f_bar.sum()])
+    a3_bar = np.outer(f_bar, w4)
+    h3_bar = a3_bar * s3 + s3_bar * gelu_d2(h3)
+    grad["W3"] = grad["W3"] + h3_bar.T @ a2     # h3 = a2 W3^T + b3
+    grad["b3"] = h3_bar.sum(axis=0)
+    a2_bar = h3_bar @ W3
+    h2_bar = a2_bar * s2 + s2_bar * gelu_d2(h2)
+    grad["W2"] = grad["W2"] + h2_bar.T @ a1     # h2 = a1 W2^T + b2
+    grad["b2"] = h2_bar.sum(axis=0)
+    a1_bar = h2_bar @ W2
+    h1_bar = a1_bar * s1 + s1_bar * gelu_d2(h1)
+    grad["W1"] = grad["W1"] + h1_bar.T @ z      # h1 = z W1^T + b1
+    grad["b1"] = h1_bar.sum(axis=0)
     flat = np.zeros(N_PARAMS)
     for name, shp, off in layout():
         flat[off:off + int(np.prod(shp))] = np.asarray(grad[name]).reshape(-1)

@@ -40,26 +40,5 @@ def build_library(out: Path | None = None, verbose: bool = False) -> Path:
     return out
 
 
-PROBES = ["probe_exp2_bias", "probe_valu_rates", "probe_mfma_f64"]
-
-
-def build_probes() -> list[Path]:
-    """Standalone gfx950 probe programs (hardware exp2 bias, VALU issue rates)."""
-    outs = []
-    for name in PROBES:
-        out = PKG / name
-        cmd = [hipcc(), "-O3", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-               str(CSRC / "probes" / (name + ".hip")), "-o", str(out)]
-        res = subprocess.run(cmd, capture_output=True, text=True)
-        if res.returncode != 0:
-            raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
-        outs.append(out)
-    return outs
-
-
 if __name__ == "__main__":
-    import sys
-
     print(build_library(verbose=True))
-    if "--probes" in sys.argv:
-        print(build_probes())

@@ -5,7 +5,7 @@ and bulk-ESS / split R-hat."""
 from .da_hmc import DAState, DelayedAcceptanceHMC
 from .mh import UnivariateMH
 from .ess import bulk_ess, ess, mcse_mean, split_rhat
-from .hmc import HMC, DualAveraging, HMCState, leapfrog
+from .hmc import HMC, DualAveraging, HMCState, NonFiniteStateError, accept_prob, leapfrog
 
 __all__ = ["DAState", "DelayedAcceptanceHMC", "bulk_ess", "ess", "mcse_mean", "split_rhat", "HMC", "DualAveraging",
-           "HMCState", "leapfrog", "UnivariateMH"]
+           "HMCState", "NonFiniteStateError", "accept_prob", "leapfrog", "UnivariateMH"]

@@ -24,7 +24,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from .hmc import HMC, HMCState, kinetic, leapfrog
+from .hmc import HMC, HMCState, accept_prob, check_state, kinetic, leapfrog
 
 
 @dataclass
@@ -58,7 +58,10 @@ class DelayedAcceptanceHMC:
     def init_state(self, z) -> DAState:
         z = np.asarray(z, dtype=np.float64)
         s, sg = self.sur(z)
-        return DAState(z, self.target.logp(z), s, sg)
+        check_state(z, s, sg, "surrogate log density")
+        lp = self.target.logp(z)
+        check_state(z, lp)
+        return DAState(z, lp, s, sg)
 
     def refresh_exact(self, st: DAState) -> DAState:
         """The target changed (a new latent-location draw): the exact value at the current point is
@@ -89,6 +92,7 @@ class DelayedAcceptanceHMC:
             if acc:
                 self.stats["accept"] += 1
                 s, sg = self.sur(new.z)
+                check_state(new.z, s, sg, "surrogate log density")
                 return DAState(new.z, new.logp, s, sg), acc, "fallback"
             return st, acc, "fallback"
         self.exact.eps = self.eps
@@ -100,18 +104,19 @@ class DelayedAcceptanceHMC:
             z1, p1, s1, sg1 = leapfrog(st.z, p0, st.s_grad, eps, self.inv_mass, self.n_leapfrog, self.sur)
         h0 = -st.s + kinetic(p0, self.inv_mass)
         h1 = -s1 + kinetic(p1, self.inv_mass)
-        a1 = float(np.exp(min(0.0, h0 - h1))) if np.isfinite(h1) else 0.0
+        a1 = accept_prob(h0 - h1)
         if not (self.rng.uniform() < a1):
             self.window.append(0.0)
             return st, False, "stage1"
         self.stats["stage1_accept"] += 1
         if st.logp is None:
             lp0, logp1 = self._exact_pair(st.z, z1)
+            check_state(st.z, lp0)
             st = DAState(st.z, lp0, st.s, st.s_grad)
         else:
             logp1 = self.target.logp(z1)
         log_a2 = (logp1 - s1) - (st.logp - st.s)
-        a2 = float(np.exp(min(0.0, log_a2))) if np.isfinite(logp1) else 0.0
+        a2 = accept_prob(log_a2)
         if self.rng.uniform() < a2:
             self.stats["stage2_accept"] += 1
             self.stats["accept"] += 1

@@ -65,6 +65,25 @@ def kinetic(p, inv_mass):
     return 0.5 * float(np.sum(inv_mass * p * p))
 
 
+def accept_prob(log_ratio) -> float:
+    """Metropolis acceptance probability min(1, exp(log_ratio)); a log ratio that is not finite (NaN from a
+    failed density evaluation, or +-inf) rejects.  (Python's min(0.0, nan) is 0.0, so the plain rule would
+    accept a NaN.)"""
+    r = float(log_ratio)
+    return float(np.exp(min(0.0, r))) if np.isfinite(r) else 0.0
+
+
+class NonFiniteStateError(RuntimeError):
+    """A chain's current point has a log density or gradient that is not finite: no valid Markov chain
+    continues from there, so the sampler stops instead of rejecting every proposal against it."""
+
+
+def check_state(z, logp, grad=None, what="log density"):
+    if not np.isfinite(logp) or (grad is not None and not np.all(np.isfinite(grad))):
+        raise NonFiniteStateError(f"{what} at the current point z = {np.asarray(z).tolist()} is not finite "
+                                  f"(value {logp}, gradient {None if grad is None else np.asarray(grad).tolist()})")
+
+
 @dataclass
 class HMCState:
     z: np.ndarray
@@ -85,8 +104,10 @@ class HMC:
         self.rng = np.random.default_rng(0) if rng is None else rng
 
     def init_state(self, z) -> HMCState:
-        logp, grad = self.target.logp_and_grad(np.asarray(z, dtype=np.float64))
-        return HMCState(np.asarray(z, dtype=np.float64), logp, grad)
+        z = np.asarray(z, dtype=np.float64)
+        logp, grad = self.target.logp_and_grad(z)
+        check_state(z, logp, grad)
+        return HMCState(z, logp, grad)
 
     def jittered_eps(self) -> float:
         """The step size of one iteration: eps, or eps (1 + jitter U(-1, 1)) with jitter > 0."""
@@ -101,7 +122,7 @@ class HMC:
                                         self.target.logp_and_grad)
         h0 = -s.logp + kinetic(p0, self.inv_mass)
         h1 = -logp1 + kinetic(p1, self.inv_mass)
-        a = float(np.exp(min(0.0, h0 - h1))) if np.isfinite(h1) else 0.0
+        a = accept_prob(h0 - h1)
         if self.rng.uniform() < a:
             return HMCState(z1, logp1, grad1), True, a
         return s, False, a

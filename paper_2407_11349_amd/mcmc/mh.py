@@ -14,6 +14,8 @@ from __future__ import annotations
 
 import numpy as np
 
+from .hmc import accept_prob, check_state
+
 
 class UnivariateMH:
     def __init__(self, target, dim=6, scales=None, rng=None, target_accept=0.44):
@@ -41,7 +43,8 @@ class UnivariateMH:
                     logp, lp = self.target.logp(z), self.target.logp(prop)
             else:
                 lp = self.target.logp(prop)
-            acc = bool(np.isfinite(lp) and np.log(self.rng.uniform()) < lp - logp)
+            check_state(z, logp)
+            acc = bool(self.rng.uniform() < accept_prob(lp - logp))
             if acc:
                 z, logp = prop, lp
             self.tries[i] += 1

@@ -1,6 +1,7 @@
 """Pins of the FP64 surrogate-network reference (oracle/mlp.py): finite differences,
 PyTorch's CPU double-backward (a library pin of the Sobolev-loss gradient), the
-Adam update against its closed form on a single step, and the BF16 rounding rule."""
+Adam update against closed forms over several steps (a constant gradient and an
+alternating one), and the BF16 rounding rule."""
 
 import numpy as np
 import pytest
@@ -73,6 +74,58 @@ def test_adam_first_step_is_sign_times_lr():
     gr = rng.normal(size=50)
     new, m, v = mlp.adam_step(th, np.zeros(50), np.zeros(50), gr, 1, 1e-3)
     np.testing.assert_allclose(new - th, -1e-3 * gr / (np.abs(gr) + 1e-8), rtol=1e-12)
+
+
+def _adam_run(grads, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    th = np.zeros_like(grads[0])
+    m, v = np.zeros_like(th), np.zeros_like(th)
+    steps = []
+    for k, gr in enumerate(grads, start=1):
+        new, m, v = mlp.adam_step(th, m, v, gr, k, lr, beta1=beta1, beta2=beta2, eps=eps)
+        steps.append(new - th)
+        th = new
+    return steps, m, v
+
+
+def test_adam_constant_gradient_closed_form():
+    """With g_t = g for every t: m_t = g (1 - beta1^t), v_t = g^2 (1 - beta2^t), so after bias correction
+    every step moves each coordinate by -lr g / (|g| + eps) (Kingma and Ba, 2015, Algorithm 1)."""
+    rng = np.random.default_rng(2)
+    g = rng.normal(size=40) * np.logspace(-3, 2, 40)
+    b1, b2, lr = 0.8, 0.95, 1e-3  # far from the defaults, so the two decay rates cannot stand in for each other
+    steps, m, v = _adam_run([g] * 6, lr, b1, b2)
+    np.testing.assert_allclose(m, g * (1.0 - b1 ** 6), rtol=1e-13)
+    np.testing.assert_allclose(v, g * g * (1.0 - b2 ** 6), rtol=1e-13)
+    for st in steps:
+        np.testing.assert_allclose(st, -lr * g / (np.abs(g) + 1e-8), rtol=1e-11)
+
+
+def test_adam_alternating_gradient_closed_form():
+    """With g_t = (-1)^(t+1) g: m_t = (1 - beta1) g (-1)^(t+1) (1 - (-beta1)^t) / (1 + beta1) (a geometric
+    series) and v_t = g^2 (1 - beta2^t), so step t moves by -lr m_t / (1 - beta1^t) / (|g| + eps)."""
+    rng = np.random.default_rng(3)
+    g = rng.normal(size=30)
+    b1, b2, lr = 0.7, 0.9, 2e-3
+    T = 5
+    steps, m, v = _adam_run([g * (-1.0) ** t for t in range(T)], lr, b1, b2)
+    for t in range(1, T + 1):
+        mt = (1.0 - b1) * g * (-1.0) ** (t + 1) * (1.0 - (-b1) ** t) / (1.0 + b1)
+        np.testing.assert_allclose(steps[t - 1], -lr * (mt / (1.0 - b1 ** t)) / (np.abs(g) + 1e-8), rtol=1e-11)
+    np.testing.assert_allclose(v, g * g * (1.0 - b2 ** T), rtol=1e-13)
+    np.testing.assert_allclose(m, (1.0 - b1) * g * (-1.0) ** (T + 1) * (1.0 - (-b1) ** T) / (1.0 + b1), rtol=1e-13)
+
+
+def test_adam_second_moment_tracks_squares():
+    """Gradients of growing size: v_t = (1 - beta2) sum_k beta2^(t-k) g_k^2 written out, against the update."""
+    g1, g2, g3 = np.array([0.5, -2.0]), np.array([1.5, 1.0]), np.array([-3.0, 0.25])
+    b1, b2, lr = 0.6, 0.85, 1e-2
+    steps, m, v = _adam_run([g1, g2, g3], lr, b1, b2)
+    m3 = (1 - b1) * (b1 * b1 * g1 + b1 * g2 + g3)
+    v3 = (1 - b2) * (b2 * b2 * g1 ** 2 + b2 * g2 ** 2 + g3 ** 2)
+    np.testing.assert_allclose(m, m3, rtol=1e-14)
+    np.testing.assert_allclose(v, v3, rtol=1e-14)
+    np.testing.assert_allclose(steps[2], -lr * (m3 / (1 - b1 ** 3)) / (np.sqrt(v3 / (1 - b2 ** 3)) + 1e-8),
+                               rtol=1e-12)
 
 
 def test_bf16_rounding_rule():

@@ -90,13 +90,19 @@ import test_mlp_oracle as mlp_pins  # noqa: E402
 
 MLP_SRC = os.path.join(ROOT, "oracle", "mlp.py")
 MLP_MUTATIONS = [
-    ("missing GELU curvature term", r"h3b = a3b \* s3 \+ u3b \* gelu_d2\(h3\) \* t3", "h3b = a3b * s3"),
-    ("transposed weight in the input gradient", r"d2 = \(d3 @ p\[\"W3\"\]\) \* s2", 'd2 = (d3 @ p["W3"].T) * s2'),
-    ("W1 gradient without the tangent term", r"grad\[\"W1\"\] = h1b\.T @ z \+ t1b\.T @ r", 'grad["W1"] = h1b.T @ z'),
+    ("missing GELU curvature term", r"h3_bar = a3_bar \* s3 \+ s3_bar \* gelu_d2\(h3\)", "h3_bar = a3_bar * s3"),
+    ("transposed weight in the input gradient", r"d2 = \(d3 @ p\[\"W3\"\]\) \* gelu_d1\(h2\)",
+     'd2 = (d3 @ p["W3"].T) * gelu_d1(h2)'),
+    ("transposed weight in the loss's reverse pass", r"c2 = d3 @ W3 ", "c2 = d3 @ W3.T "),
+    ("W1 gradient without the reverse-pass term", r"grad\[\"W1\"\] = d1\.T @ gz_bar", 'grad["W1"] = 0.0 * gz_bar.T @ d1'),
+    ("slope adjoint from the wrong factor", r"s2_bar = d2_bar \* c2", "s2_bar = d2_bar * s2"),
     ("GELU derivative without x phi(x)", r"return 0\.5 \* \(1\.0 \+ _erf\(x / _SQ2\)\) \+ x \* _ISQ2PI \* np\.exp\(-0\.5 \* x \* x\)",
      "return 0.5 * (1.0 + _erf(x / _SQ2))"),
     ("Adam without bias correction", r"mh = m / \(1\.0 - beta1 \*\* step\)", "mh = m"),
-    ("gradient-matching weight dropped", r"ct = \(2\.0 \* lam / B\)", "ct = 0.0"),
+    ("Adam first moment decayed by beta2", r"m = beta1 \* m \+", "m = beta2 * m +"),
+    ("Adam second moment decayed by beta1", r"v = beta2 \* v \+", "v = beta1 * v +"),
+    ("Adam second moment bias-corrected with beta1", r"vh = v / \(1\.0 - beta2 \*\* step\)", "vh = v / (1.0 - beta1 ** step)"),
+    ("gradient-matching weight dropped", r"gz_bar = \(2\.0 \* lam / B\) \* r", "gz_bar = 0.0 * r"),
 ]
 MLP_PIN_TESTS = [name for name in dir(mlp_pins) if name.startswith("test_")]
 
