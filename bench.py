@@ -270,6 +270,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=None, help="override the event count (testing only)")
+    ap.add_argument("--workspace-mib", type=int, default=0,
+                    help="FP32 workspace size (default: hawkes_workspace_bytes); more room means fewer passes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-skip", action="store_true", help="do not time the FP32 skip mode")
@@ -325,7 +327,7 @@ def main():
         print(json.dumps({"workload": cfg.name, "n_events": n,
                           "components": component_timings(hk, torch, county, rect, dev.x, dev.y)}), flush=True)
         return
-    ws = hk.Workspace(n, "fp32")
+    ws = hk.Workspace(n, "fp32", nbytes=(args.workspace_mib << 20) if args.workspace_mib else None)
     out_ll = torch.empty(1, dtype=torch.float64, device="cuda")
     out_g = torch.empty(6, dtype=torch.float64, device="cuda")
     seed = 2002
@@ -337,9 +339,9 @@ def main():
     flop_executed = (FLOP_BG + FLOP_COL) * bg_pairs // 2 + FLOP_TRIG * causal_pairs
     exp_executed = bg_pairs // 2 + causal_pairs
 
-    def step(it):
+    def step(it, timer=None):
         hk.resample_locations(county, rect, seed, it, dev.x, dev.y)
-        hk.loglik_grad(dev, th, precision="fp32", ws=ws, out=out_ll, grad=out_g)
+        hk.loglik_grad(dev, th, precision="fp32", ws=ws, out=out_ll, grad=out_g, timer=timer)
 
     log(f"bench: n={n} warmup={args.warmup} steps={args.steps}")
     for it in range(args.warmup):
@@ -347,17 +349,17 @@ def main():
         torch.cuda.synchronize()
         log(f"warmup step {it} done: loglik {out_ll.item():.6f}")
 
-    hk.set_timing(True)
-    kernel_ms = []
+    # one pair of caller-owned HIP events per step, recorded by the library around the pair sweep on
+    # the step's stream and read after the timed region (no host synchronisation inside it)
+    timers = [hk.SweepTimer() for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(args.warmup + k)
-        kernel_ms.append(hk.last_pair_kernel_ms())
+        step(args.warmup + k, timers[k])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    hk.set_timing(False)
-    log(f"timed {args.steps} steps in {elapsed:.3f} s; pair kernel ms {['%.2f' % v for v in kernel_ms]}")
+    kernel_ms = [tm.elapsed_ms() for tm in timers]
+    log(f"timed {args.steps} steps in {elapsed:.3f} s; pair sweep ms {['%.2f' % v for v in kernel_ms]}")
     ll_last = float(out_ll.item())
     assert np.isfinite(ll_last) and ws.status() == 0
 
@@ -412,10 +414,9 @@ def main():
     # the forward-only sweep (log-likelihood without gradient: the exact evaluations of the delayed-acceptance
     # correction); reported apart from the loglik+grad metric
     hk.loglik(dev, th, precision="fp32", ws=ws, out=out_ll)
-    hk.set_timing(True)
-    hk.loglik(dev, th, precision="fp32", ws=ws, out=out_ll)
-    kms_fwd = hk.last_pair_kernel_ms()
-    hk.set_timing(False)
+    tm = hk.SweepTimer()
+    hk.loglik(dev, th, precision="fp32", ws=ws, out=out_ll, timer=tm)
+    kms_fwd = tm.elapsed_ms()
     torch.cuda.synchronize()
     result["fp32_loglik_only"] = {"kernel_ms": kms_fwd, "pairs_per_s": pairs / (kms_fwd / 1e3),
                                   "note": "forward-only sweep (S0, G0 per target), pair kernel time"}
@@ -426,10 +427,9 @@ def main():
     th2 = np.stack([th, th * np.array([1.02, 0.98, 1.03, 0.97, 1.02, 0.98])])
     out2 = torch.empty(2, dtype=torch.float64, device="cuda")
     hk.loglik_batch(dev, th2, precision="fp32", ws=ws, out=out2)
-    hk.set_timing(True)
-    hk.loglik_batch(dev, th2, precision="fp32", ws=ws, out=out2)
-    kms_b2 = hk.last_pair_kernel_ms()
-    hk.set_timing(False)
+    tm = hk.SweepTimer()
+    hk.loglik_batch(dev, th2, precision="fp32", ws=ws, out=out2, timer=tm)
+    kms_b2 = tm.elapsed_ms()
     torch.cuda.synchronize()
     result["fp32_loglik_batch2"] = {
         "kernel_ms": kms_b2, "cost_vs_one_vector": kms_b2 / kms_fwd,
@@ -445,10 +445,9 @@ def main():
         g_s = torch.empty(6, dtype=torch.float64, device="cuda")
         hk.loglik_grad(dev, th, precision="fp32_skip", ws=wss, out=ll_s, grad=g_s)
         hk.loglik_grad(dev, th, precision="fp32", ws=ws, out=out_ll, grad=out_g)
-        hk.set_timing(True)
-        hk.loglik_grad(dev, th, precision="fp32_skip", ws=wss, out=ll_s, grad=g_s)
-        kms_skip = hk.last_pair_kernel_ms()
-        hk.set_timing(False)
+        tm = hk.SweepTimer()
+        hk.loglik_grad(dev, th, precision="fp32_skip", ws=wss, out=ll_s, grad=g_s, timer=tm)
+        kms_skip = tm.elapsed_ms()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         hk.loglik_grad(dev, th, precision="fp32_skip", ws=wss, out=ll_s, grad=g_s)

@@ -28,8 +28,12 @@
  *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
  *    asynchronously on it; outputs are valid after the caller synchronises.
  *  - No call allocates device memory: scratch space comes from the
- *    caller-provided workspace `ws` of at least hawkes_workspace_bytes() bytes,
- *    256-byte aligned.  Calls that share a workspace must not overlap.
+ *    caller-provided workspace `ws` of hawkes_workspace_bytes() bytes (at
+ *    least hawkes_workspace_min_bytes()), 256-byte aligned.  Calls that share a workspace must not overlap; calls
+ *    with distinct workspaces are independent (the library keeps no state
+ *    between calls other than the calling thread's last-error message).
+ *  - `opts` (may be NULL) carries per-call tuning and timing; see
+ *    hawkes_options.
  *  - Return value: HAWKES_OK (0) or a negative status; no C++ exception
  *    crosses the ABI.  hawkes_last_error() gives a message for the calling
  *    thread's last failure.
@@ -89,31 +93,73 @@ typedef struct hawkes_events {
  * those tiles' triggering terms; the work falls when the time span is long
  * against tau_t and 1/omega.
  * Results are bitwise reproducible for a given event set, theta, precision,
- * row range and tuning (below). */
+ * row range and options (hawkes_options). */
 enum hawkes_precision { HAWKES_FP64 = 0, HAWKES_FP32 = 1, HAWKES_FP32_SKIP = 2 };
 
 enum hawkes_status {
     HAWKES_OK = 0,
     HAWKES_EINVAL = -1,     /* null pointer, n < 1, n too large, bad precision, theta not finite/positive */
     HAWKES_ERANGE = -2,     /* not 0 <= row_begin <= row_end <= n */
-    HAWKES_EWORKSPACE = -3, /* workspace null, misaligned or smaller than hawkes_workspace_bytes() */
+    HAWKES_EWORKSPACE = -3, /* workspace null, misaligned or too small (hawkes_workspace_min_bytes) */
     HAWKES_EHIP = -4,       /* a HIP runtime call failed; see hawkes_last_error() */
     HAWKES_EORDER = -5,     /* device check: times not nondecreasing */
     HAWKES_EDATA = -6       /* device check: a non-finite value or s <= 0 */
 };
 
+/* Per-call options (all-zero = defaults).
+ *   row_workgroups    row sweep (a row range, or symmetric_groups = -1): the
+ *                     workgroups (target blocks x source chunks) a call aims
+ *                     for; 0 = 32768, else 1..65536.
+ *   symmetric_groups  whole-set calls (row range [0, n)): the symmetric
+ *                     sweep's number of row groups (and as many column
+ *                     groups; one workgroup per pair of groups it needs);
+ *                     0 = 384, 1..1024, or -1: whole-set calls take the row
+ *                     sweep too.
+ *   timing_start, timing_stop
+ *                     hipEvent_t handles (both or neither): recorded on the
+ *                     call's stream right before the first pair-sweep launch
+ *                     and right after the last one (with the fold of its
+ *                     partial sums), so that hipEventElapsedTime gives the
+ *                     sweep's duration.  The caller creates and owns them.
+ * Results do not depend on the options beyond the FP64 summation order of
+ * partial sums (symmetric_groups = -1 also changes the order of the FP32
+ * background sums), nor on the workspace size.  Values out of range:
+ * HAWKES_EINVAL. */
+typedef struct hawkes_options {
+    int64_t row_workgroups;
+    int32_t symmetric_groups;
+    int32_t reserved;  /* must be 0 */
+    void *timing_start;
+    void *timing_stop;
+} hawkes_options;
+
 /* Bytes of workspace the likelihood calls need for n events at `precision`
- * (0 if the arguments are invalid).  FP64: linear in n.  FP32: the symmetric
- * sweep keeps 9 doubles per event for each of up to 384 event groups (about
- * 24 GB at n = 10^6), so the size grows with n as n * min(n / 512, 384). */
+ * (0 if the arguments are invalid): a part linear in n (staged source
+ * records, per-row FP64 accumulators and values; about 210 bytes per event
+ * at FP32) plus a slot region for the partial sums of the sweep's
+ * workgroups.  The sweep runs in passes over as many workgroups as the slot
+ * region holds, each pass followed by a fold of its partial sums into the
+ * per-row accumulators; the returned size gives the slot region the smaller
+ * of 768 MiB and what a single pass needs (at least one workgroup's slot):
+ * about 0.97 GiB in all at n = 10^6 (FP32).  A larger workspace means fewer
+ * passes and the same results. */
 size_t hawkes_workspace_bytes(int64_t n, int precision);
+
+/* The smallest workspace the calls accept for n events at `precision` with
+ * default options (0 if the arguments are invalid): the part linear in n and
+ * the slot of one workgroup, so that the sweep runs one workgroup per pass.
+ * Between this and hawkes_workspace_bytes() the results are the same and
+ * only the number of passes changes.  Options that enlarge a workgroup's
+ * slot (fewer symmetric groups) may need more: such calls return
+ * HAWKES_EWORKSPACE. */
+size_t hawkes_workspace_min_bytes(int64_t n, int precision);
 
 /* Log-likelihood of rows [row_begin, row_end):  *d_loglik = sum_n l_n
  * (paper equation "model").  d_loglik: device pointer to 1 double.
  * Empty row ranges give 0. */
 int hawkes_loglik(const hawkes_events *events, const hawkes_theta *theta, int precision,
                   int64_t row_begin, int64_t row_end, void *ws, size_t ws_bytes,
-                  double *d_loglik, void *stream);
+                  double *d_loglik, const hawkes_options *opts, void *stream);
 
 /* As hawkes_loglik, plus the gradient of the same row sum with respect to
  * theta, in the order (mu, tau_x, tau_t, xi, h0, omega): d_grad is a device
@@ -121,7 +167,7 @@ int hawkes_loglik(const hawkes_events *events, const hawkes_theta *theta, int pr
  * over the pairs.  A floored event contributes no gradient from its log term. */
 int hawkes_loglik_grad(const hawkes_events *events, const hawkes_theta *theta, int precision,
                        int64_t row_begin, int64_t row_end, void *ws, size_t ws_bytes,
-                       double *d_loglik, double *d_grad, void *stream);
+                       double *d_loglik, double *d_grad, const hawkes_options *opts, void *stream);
 
 /* Per-event terms of rows [row_begin, row_end): d_lambda[r] = lambda_n and
  * d_comp[r] = Lambda_n for n = row_begin + r (device arrays of
@@ -129,7 +175,7 @@ int hawkes_loglik_grad(const hawkes_events *events, const hawkes_theta *theta, i
  * sweep as hawkes_loglik. */
 int hawkes_event_terms(const hawkes_events *events, const hawkes_theta *theta, int precision,
                        int64_t row_begin, int64_t row_end, void *ws, size_t ws_bytes,
-                       double *d_lambda, double *d_comp, void *stream);
+                       double *d_lambda, double *d_comp, const hawkes_options *opts, void *stream);
 
 /* Log-likelihoods of rows [row_begin, row_end) for num_theta parameter vectors
  * on the same events: d_loglik[k] = the hawkes_loglik value at thetas[k]
@@ -149,7 +195,7 @@ int hawkes_event_terms(const hawkes_events *events, const hawkes_theta *theta, i
  * hawkes_workspace_bytes(n, precision). */
 int hawkes_loglik_batch(const hawkes_events *events, const hawkes_theta *thetas, int64_t num_theta,
                         int precision, int64_t row_begin, int64_t row_end, void *ws, size_t ws_bytes,
-                        double *d_loglik, void *stream);
+                        double *d_loglik, const hawkes_options *opts, void *stream);
 
 /* The X-update of the cut posterior (paper Section 2.2: latent locations drawn
  * from p(X | coarsened data) in O(N), uniformly within each event's county),
@@ -169,29 +215,6 @@ int hawkes_resample_locations(int64_t n, const int32_t *d_county, const double *
  * written by the last likelihood call that used it: *status = HAWKES_OK,
  * HAWKES_EORDER or HAWKES_EDATA. */
 int hawkes_workspace_status(const void *ws, int *status, void *stream);
-
-/* Timing of the dominant pair-sweep kernel: when enabled, each likelihood
- * call records HIP events around that kernel on the caller's stream, and
- * hawkes_last_pair_kernel_ms() waits for the last one and returns its
- * duration in milliseconds. */
-int hawkes_set_timing(int enable);
-int hawkes_last_pair_kernel_ms(float *ms);
-
-/* Tuning: the number of workgroups the row sweep (FP64, and FP32 over a row
- * range) aims for per call (the source range is split into chunks so that
- * target blocks x chunks is about this many; 1 <= wgs <= 65536; default
- * 32768).  Results do not depend on it
- * beyond FP rounding of the chunk partial sums.  Process-wide setting. */
-int hawkes_tune_target_workgroups(int64_t wgs);
-
-/* Tuning: the symmetric FP32 sweep over the whole event set splits the
- * events into about `groups` row groups and as many column groups (one
- * workgroup per pair of groups it needs, about groups^2 / 2);
- * 0 <= groups <= 384, default 384; 0 makes whole-set calls take the row
- * sweep too.  Results do not depend on it beyond FP64 summation order of the
- * partial sums (0 changes the order of the FP32 background sums as well).
- * Process-wide setting. */
-int hawkes_tune_symmetric_groups(int64_t groups);
 
 /* Message for a status code, and the calling thread's last error message. */
 const char *hawkes_strerror(int status);

@@ -5,10 +5,10 @@ run in hand-written HIP kernels for gfx950 behind the C ABI of
 include/hawkes.h (libhawkes.so); this package is the thin Python binding.
 """
 
-from .likelihood import (DeviceEvents, HawkesLoglik, Workspace, event_terms, hawkes_loglik, last_pair_kernel_ms,
-                         loglik, loglik_batch, loglik_grad, resample_locations, set_timing, workspace_bytes)
+from .likelihood import (DeviceEvents, HawkesLoglik, SweepTimer, Workspace, event_terms, hawkes_loglik, loglik,
+                         loglik_batch, loglik_grad, resample_locations, workspace_bytes, workspace_min_bytes)
 
 __all__ = [
-    "DeviceEvents", "HawkesLoglik", "Workspace", "event_terms", "hawkes_loglik", "last_pair_kernel_ms", "loglik",
-    "loglik_batch", "loglik_grad", "resample_locations", "set_timing", "workspace_bytes",
+    "DeviceEvents", "HawkesLoglik", "SweepTimer", "Workspace", "event_terms", "hawkes_loglik", "loglik",
+    "loglik_batch", "loglik_grad", "resample_locations", "workspace_bytes", "workspace_min_bytes",
 ]

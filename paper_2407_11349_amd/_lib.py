@@ -27,9 +27,8 @@ HAWKES_EDATA = -6
 
 # every entry point declared in include/hawkes.h
 EXPORTS = (
-    "hawkes_workspace_bytes", "hawkes_loglik", "hawkes_loglik_grad", "hawkes_event_terms",
-    "hawkes_loglik_batch", "hawkes_resample_locations", "hawkes_workspace_status", "hawkes_set_timing",
-    "hawkes_last_pair_kernel_ms", "hawkes_tune_target_workgroups", "hawkes_tune_symmetric_groups",
+    "hawkes_workspace_bytes", "hawkes_workspace_min_bytes", "hawkes_loglik", "hawkes_loglik_grad", "hawkes_event_terms",
+    "hawkes_loglik_batch", "hawkes_resample_locations", "hawkes_workspace_status",
     "hawkes_strerror", "hawkes_last_error",
     # include/hawkes_mlp.h
     "hawkes_mlp_state_bytes", "hawkes_mlp_workspace_bytes", "hawkes_mlp_load", "hawkes_mlp_store",
@@ -37,8 +36,10 @@ EXPORTS = (
 )
 # hawkes_mlp_leapfrog_io: 42 doubles (z, p, grad, inv_mass, m_z, s_z: 6 each; m_y, s_y, prior_var, eps, s, status)
 LEAPFROG_IO_DOUBLES = 42
-# default (and largest) group count of the symmetric FP32 sweep (hawkes_tune_symmetric_groups)
+# hawkes_options.symmetric_groups: the library's default and largest accepted counts
 SYM_GROUPS_DEFAULT = 384
+SYM_GROUPS_MAX = 1024
+ROW_WGS_MAX = 65536
 MLP_PARAMS = 133633
 
 
@@ -49,6 +50,13 @@ class Theta(ctypes.Structure):
 class Events(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("t", ctypes.c_void_p), ("x", ctypes.c_void_p),
                 ("y", ctypes.c_void_p), ("s", ctypes.c_void_p), ("area", ctypes.c_double)]
+
+
+class Options(ctypes.Structure):
+    """hawkes_options: per-call tuning and timing (all-zero = defaults)."""
+
+    _fields_ = [("row_workgroups", ctypes.c_int64), ("symmetric_groups", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("timing_start", ctypes.c_void_p), ("timing_stop", ctypes.c_void_p)]
 
 
 class HawkesError(RuntimeError):
@@ -73,17 +81,17 @@ def load(path: Path | str | None = None) -> ctypes.CDLL:
     ev_p, th_p = ctypes.POINTER(Events), ctypes.POINTER(Theta)
     lib.hawkes_workspace_bytes.argtypes = [i64, ctypes.c_int]
     lib.hawkes_workspace_bytes.restype = ctypes.c_size_t
+    lib.hawkes_workspace_min_bytes.argtypes = [i64, ctypes.c_int]
+    lib.hawkes_workspace_min_bytes.restype = ctypes.c_size_t
     common = [ev_p, th_p, ctypes.c_int, i64, i64, vp, ctypes.c_size_t]
-    lib.hawkes_loglik.argtypes = common + [vp, vp]
-    lib.hawkes_loglik_grad.argtypes = common + [vp, vp, vp]
-    lib.hawkes_event_terms.argtypes = common + [vp, vp, vp]
-    lib.hawkes_loglik_batch.argtypes = [ev_p, th_p, i64, ctypes.c_int, i64, i64, vp, ctypes.c_size_t, vp, vp]
+    opt_p = ctypes.POINTER(Options)
+    lib.hawkes_loglik.argtypes = common + [vp, opt_p, vp]
+    lib.hawkes_loglik_grad.argtypes = common + [vp, vp, opt_p, vp]
+    lib.hawkes_event_terms.argtypes = common + [vp, vp, opt_p, vp]
+    lib.hawkes_loglik_batch.argtypes = [ev_p, th_p, i64, ctypes.c_int, i64, i64, vp, ctypes.c_size_t, vp, opt_p,
+                                        vp]
     lib.hawkes_resample_locations.argtypes = [i64, vp, vp, i32, u64, u64, vp, vp, vp]
     lib.hawkes_workspace_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int), vp]
-    lib.hawkes_set_timing.argtypes = [ctypes.c_int]
-    lib.hawkes_last_pair_kernel_ms.argtypes = [ctypes.POINTER(ctypes.c_float)]
-    lib.hawkes_tune_target_workgroups.argtypes = [i64]
-    lib.hawkes_tune_symmetric_groups.argtypes = [i64]
     lib.hawkes_mlp_state_bytes.argtypes = []
     lib.hawkes_mlp_state_bytes.restype = ctypes.c_size_t
     lib.hawkes_mlp_workspace_bytes.argtypes = [i64]
@@ -101,8 +109,7 @@ def load(path: Path | str | None = None) -> ctypes.CDLL:
     lib.hawkes_last_error.restype = ctypes.c_char_p
     for name in ("hawkes_loglik", "hawkes_loglik_grad", "hawkes_event_terms", "hawkes_loglik_batch",
                  "hawkes_resample_locations",
-                 "hawkes_workspace_status", "hawkes_set_timing", "hawkes_last_pair_kernel_ms",
-                 "hawkes_tune_target_workgroups", "hawkes_tune_symmetric_groups", "hawkes_mlp_load",
+                 "hawkes_workspace_status", "hawkes_mlp_load",
                  "hawkes_mlp_store", "hawkes_mlp_forward", "hawkes_mlp_leapfrog", "hawkes_mlp_loss_grad",
                  "hawkes_mlp_adam_step"):
         getattr(lib, name).restype = ctypes.c_int
@@ -151,3 +158,67 @@ def theta_array(thetas):
 
 def ptr(t: torch.Tensor | None) -> int | None:
     return None if t is None else int(t.data_ptr())
+
+
+def options(row_workgroups: int = 0, symmetric_groups: int = 0, timer=None):
+    """A hawkes_options struct for a call (None when every field keeps its default)."""
+    if not row_workgroups and not symmetric_groups and timer is None:
+        return None
+    o = Options(int(row_workgroups), int(symmetric_groups), 0, None, None)
+    if timer is not None:
+        o.timing_start, o.timing_stop = timer.handles()
+    return o
+
+
+def opt_ref(o):
+    return None if o is None else ctypes.byref(o)
+
+
+_hip = None
+
+
+def hip_runtime() -> ctypes.CDLL:
+    """The HIP runtime the library and torch share (loaded once by soname), for the caller-owned
+    timing events of hawkes_options."""
+    global _hip
+    if _hip is None:
+        torch.cuda.init()
+        hip = ctypes.CDLL("libamdhip64.so.7")
+        vp = ctypes.c_void_p
+        hip.hipEventCreate.argtypes = [ctypes.POINTER(vp)]
+        hip.hipEventDestroy.argtypes = [vp]
+        hip.hipEventSynchronize.argtypes = [vp]
+        hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), vp, vp]
+        for f in (hip.hipEventCreate, hip.hipEventDestroy, hip.hipEventSynchronize, hip.hipEventElapsedTime):
+            f.restype = ctypes.c_int
+        _hip = hip
+    return _hip
+
+
+class SweepTimer:
+    """Two HIP events that a call records around its pair sweep (hawkes_options.timing_start/stop);
+    elapsed_ms() waits for the stop event and returns the sweep's duration on the device."""
+
+    def __init__(self):
+        hip = hip_runtime()
+        self._start, self._stop = ctypes.c_void_p(), ctypes.c_void_p()
+        for e in (self._start, self._stop):
+            if hip.hipEventCreate(ctypes.byref(e)) != 0:
+                raise RuntimeError("hipEventCreate failed")
+
+    def handles(self):
+        return self._start.value, self._stop.value
+
+    def elapsed_ms(self) -> float:
+        hip = hip_runtime()
+        ms = ctypes.c_float(0.0)
+        if hip.hipEventSynchronize(self._stop) != 0 or hip.hipEventElapsedTime(ctypes.byref(ms), self._start,
+                                                                                self._stop) != 0:
+            raise RuntimeError("timing events were not recorded")
+        return float(ms.value)
+
+    def __del__(self):
+        if _hip is not None:
+            for e in (getattr(self, "_start", None), getattr(self, "_stop", None)):
+                if e is not None and e.value:
+                    _hip.hipEventDestroy(e)

@@ -101,11 +101,20 @@ constexpr int NW = WG / 64;               // waves per workgroup
 constexpr int KT = HAWKES_KT;             // target rows per lane
 constexpr int TB = WG * KT;               // target rows per workgroup
 constexpr int GS = HAWKES_GS;             // FP32 terms summed before folding into FP64
-constexpr int64_t MAX_TARGET_WGS = 65536; // upper bound used for workspace sizing
-// row / column groups of the symmetric sweep (workspace bound): 384 splits
-// 10^6 events into 326 x 326 groups of 6 blocks, whose ~53,000 workgroups
-// leave a shorter tail than 160 groups (151 x 151 of 13 blocks) did
-constexpr int MAX_SYM_GROUPS = 384;
+// row sweep: workgroups (target blocks x source chunks) a call aims for
+constexpr int64_t DEFAULT_ROW_WGS = 32768;
+constexpr int64_t MAX_ROW_WGS = 65536;
+// row / column groups of the symmetric sweep: 384 splits 10^6 events into
+// 326 x 326 groups of 6 blocks, whose ~53,000 workgroups leave a shorter tail
+// than 160 groups (151 x 151 of 13 blocks) did
+constexpr int DEFAULT_SYM_GROUPS = 384;
+constexpr int MAX_SYM_GROUPS = 1024;
+// Partial sums of the sweep's workgroups ("cells") go to slots that a fold
+// kernel adds into per-row FP64 accumulators after each pass over at most as
+// many cells as the slot region holds; the default region is this large (or
+// what one pass over every cell needs, if less): with the part linear in n,
+// under 1 GiB of workspace at 10^6 events.
+constexpr size_t DEFAULT_SLOT_BYTES = size_t(768) << 20;
 constexpr int MAX_FUSED_THETA = 2;        // parameter vectors one batched sweep evaluates together
 constexpr int64_t MAX_N = int64_t(1) << 30;
 constexpr double LOG2E = 1.4426950408889634074;
@@ -150,8 +159,7 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Groups of the symmetric sweep: about `groups` row groups of rr target
 // blocks and as many column groups of ct = KT rr source tiles (the same
-// number of events), so the workgroup count is about groups^2 / 2 and the
-// partials take 9 doubles per row and group.
+// number of events), so the workgroup count is about groups^2 / 2.
 struct SymPlan {
     int rr = 1, ct = 1, num_gr = 0, num_gc = 0;
 };
@@ -167,8 +175,6 @@ SymPlan make_sym_plan(int64_t num_tb, int64_t num_tiles, int groups)
     return S;
 }
 
-int g_sym_groups = MAX_SYM_GROUPS;
-
 // Per-source FP32 record fields in 8-byte slots (pairs), so that one index
 // scale addresses every field of a source in LDS.
 struct DeltaGroup {
@@ -176,13 +182,56 @@ struct DeltaGroup {
     int g;    // tie-group id
 };
 
+// Workspace: a fixed part that grows linearly with n (staged records, per-row
+// accumulators and values) followed by the slot region of the passes, whose
+// size is whatever the caller's workspace leaves (at least one cell).
 struct Layout {
-    int64_t n = 0, n_pad = 0, num_tiles = 0, part_elems = 0, max_blocks = 0, rows_cap = 0;
+    int64_t n = 0, n_pad = 0, num_tiles = 0, max_blocks = 0, rows_cap = 0;
     size_t status = 0, g = 0, tile = 0, rowvals = 0, rescue = 0;
     size_t xs = 0, ys = 0, tsd = 0, r2 = 0, v2 = 0, u2 = 0, dg = 0;
-    size_t sblk = 0, eblk = 0, gchi = 0, g0 = 0;
-    size_t partials = 0, blocks = 0, total = 0;
+    size_t sblk = 0, eblk = 0, gchi = 0, g0 = 0, rowstart = 0;
+    size_t acc = 0, blocks = 0, slots = 0, fixed = 0;
+    size_t total = 0;    // the size hawkes_workspace_bytes returns
+    size_t minimum = 0;  // the fixed part and one cell of the default plans
 };
+
+// Bytes of one cell's slot: row sums (6 per row) and, in the symmetric sweep,
+// column sums (3 per source) of its group's events.
+inline size_t sym_cell_bytes(const SymPlan &S) { return sizeof(double) * 9 * size_t(S.rr) * TB; }
+inline size_t row_cell_bytes() { return sizeof(double) * 6 * size_t(TB); }
+
+// Work plan of the row sweep: target blocks over the row range, source chunks.
+struct Plan {
+    int64_t rows = 0, num_tb = 0, rows_pad = 0, chunk_tiles = 0, num_chunks = 0;
+};
+
+Plan make_plan(int64_t rows, int64_t num_tiles, int64_t target_wgs)
+{
+    Plan P;
+    P.rows = rows;
+    P.num_tb = ceil_div(rows, TB);
+    P.rows_pad = P.num_tb * TB;
+    int64_t want = ceil_div(target_wgs, P.num_tb);
+    if (want < 1)
+        want = 1;
+    if (want > num_tiles)
+        want = num_tiles;
+    P.chunk_tiles = ceil_div(num_tiles, want);
+    P.num_chunks = ceil_div(num_tiles, P.chunk_tiles);
+    return P;
+}
+
+// Slot bytes a call with the default tuning needs for a single pass (the
+// symmetric sweep's bound counts every row group x column group cell).
+size_t single_pass_bytes(int64_t n)
+{
+    const int64_t num_tiles = ceil_div(n, TS), tb = ceil_div(n, TB);
+    const SymPlan S = make_sym_plan(tb, num_tiles, DEFAULT_SYM_GROUPS);
+    const size_t sym = size_t(S.num_gr) * size_t(S.num_gc) * sym_cell_bytes(S);
+    const Plan P = make_plan(n, num_tiles, DEFAULT_ROW_WGS);
+    const size_t row = size_t(P.num_tb) * size_t(P.num_chunks) * row_cell_bytes();
+    return sym > row ? sym : row;
+}
 
 Layout make_layout(int64_t n, int precision)
 {
@@ -193,18 +242,6 @@ Layout make_layout(int64_t n, int precision)
     const int64_t tb_max = ceil_div(n, TB);
     L.max_blocks = ceil_div(n, WG);
     L.rows_cap = tb_max * TB;
-    // row sweep: target blocks x chunks partial slots of 6 sums
-    int64_t slots = L.num_tiles * tb_max;
-    if (slots > MAX_TARGET_WGS + tb_max)
-        slots = MAX_TARGET_WGS + tb_max;
-    L.part_elems = slots * TB * 6;
-    {
-        // symmetric sweep at the largest group count: 6 row and 3 column sums per group
-        const SymPlan S = make_sym_plan(tb_max, L.num_tiles, MAX_SYM_GROUPS);
-        const int64_t sym_elems = (6 * int64_t(S.num_gc) + 3 * int64_t(S.num_gr)) * L.rows_cap;
-        if (sym_elems > L.part_elems)
-            L.part_elems = sym_elems;
-    }
 
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -229,35 +266,65 @@ Layout make_layout(int64_t n, int precision)
     L.eblk = take(sizeof(int) * tb_max);
     L.gchi = take(sizeof(int) * MAX_SYM_GROUPS);
     L.g0 = take(sizeof(int) * MAX_SYM_GROUPS);
-    L.partials = take(sizeof(double) * L.part_elems);
+    L.rowstart = take(sizeof(int) * (MAX_SYM_GROUPS + 1));  // + the symmetric plan's cell count
+    // per-row FP64 accumulators of the folded partial sums: 6 row sums, 3 column sums
+    L.acc = take(sizeof(double) * 9 * L.rows_cap);
     L.blocks = take(sizeof(double) * 7 * L.max_blocks);
     L.rowvals = take(sizeof(double) * 7 * L.rows_cap);
     L.rescue = take(sizeof(int) * L.rows_cap);
-    L.total = off;
+    L.slots = off;
+    L.fixed = off;
+    size_t slot_bytes = single_pass_bytes(n);
+    if (slot_bytes > DEFAULT_SLOT_BYTES)
+        slot_bytes = DEFAULT_SLOT_BYTES;
+    // at least one cell of the default plans (a symmetric cell is never smaller than a row cell)
+    const SymPlan S1 = make_sym_plan(tb_max, L.num_tiles, DEFAULT_SYM_GROUPS);
+    const size_t one_cell = sym_cell_bytes(S1);
+    if (slot_bytes < one_cell)
+        slot_bytes = one_cell;
+    L.total = align256(off + slot_bytes);
+    L.minimum = align256(off + one_cell);
     return L;
 }
 
-// Work plan of the row sweep: target blocks over the row range, source chunks.
-struct Plan {
-    int64_t rows = 0, num_tb = 0, rows_pad = 0, chunk_tiles = 0, num_chunks = 0;
+// Device view of the cells of a sweep, numbered in launch order: row groups
+// from the latest down, and within a row group the column groups it reaches
+// from the earliest up.  Symmetric sweep: row group gr reaches column groups
+// 0..gchi[gr] (from the device plan) and its first cell is rowstart[gr];
+// row sweep (rowstart == nullptr): every target block takes every chunk.
+struct CellMap {
+    const int *rowstart = nullptr, *gchi = nullptr;
+    const int *total = nullptr;  // symmetric sweep: the plan's cell count
+    int num_gr = 0, num_gc = 0;
+    int cell0 = 0;               // first cell of the pass being launched
 };
 
-int64_t g_target_wgs = 32768;
-
-Plan make_plan(int64_t rows, int64_t num_tiles)
+// Cell of workgroup w of the current pass (false: past the last cell).
+__host__ __device__ inline bool map_cell(const CellMap &m, unsigned w, int &gr, int &gc)
 {
-    Plan P;
-    P.rows = rows;
-    P.num_tb = ceil_div(rows, TB);
-    P.rows_pad = P.num_tb * TB;
-    int64_t want = ceil_div(g_target_wgs, P.num_tb);
-    if (want < 1)
-        want = 1;
-    if (want > num_tiles)
-        want = num_tiles;
-    P.chunk_tiles = ceil_div(num_tiles, want);
-    P.num_chunks = ceil_div(num_tiles, P.chunk_tiles);
-    return P;
+    const int c = m.cell0 + int(w);
+    if (!m.rowstart) {
+        if (c >= m.num_gr * m.num_gc)
+            return false;
+        gr = m.num_gr - 1 - c / m.num_gc;
+        gc = c % m.num_gc;
+        return true;
+    }
+    if (c >= *m.total)
+        return false;
+    // rowstart decreases with gr and rowstart[num_gr - 1] = 0: the smallest
+    // gr whose first cell is at or before c owns c
+    int lo = 0, hi = m.num_gr - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (m.rowstart[mid] <= c)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    gr = lo;
+    gc = c - m.rowstart[lo];
+    return true;
 }
 
 // ------------------------------------------------------------- kernels
@@ -436,11 +503,12 @@ struct PairF32 {
     // every time in blocks < sblk[b] is below every time in b, and every
     // time in blocks >= eblk[b] is above every time in b.
     const int *sblk, *eblk;
-    double *prow;  // [num_gc][6][rows_pad]: row sums of the rows against one column group
-    double *pcol;  // [num_gr][3][rows_pad]: background column sums from one row group
+    CellMap cells;  // the cells of the sweep and the first one of this pass
+    double *srow;   // [slot][6][ge]: a cell's row sums of its row group's rows
+    double *scol;   // [slot][3][ge]: a cell's background column sums of its column group's sources
+    int ge;         // events per group (slot stride)
     int row_begin, row_end, rows_pad, num_tiles, num_tb;  // indices below 2^31 (n <= 2^30)
-    int rr, ct;          // target blocks per row group, source tiles per column group
-    int num_gr, num_gc;  // group counts; the grid is num_gr x num_gc workgroups
+    int rr, ct;     // target blocks per row group, source tiles per column group
     int sym;
     // Skip mode: every background term of a pair further apart in time than
     // skip_gap days is exactly zero in FP32.  Tiles that far before a block
@@ -594,21 +662,20 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
 
     constexpr int UJ = GRAD ? HAWKES_UJ_GRAD : HAWKES_UJ;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15;
-    const int gr = a.num_gr - 1 - int(blockIdx.x / unsigned(a.num_gc));  // latest row groups first
-    const int gc = int(blockIdx.x % unsigned(a.num_gc));
+    int gr, gc;
+    if (!map_cell(a.cells, blockIdx.x, gr, gc))
+        return;
     const int b_first = gr * a.rr;
     const int b_stop = (b_first + a.rr < a.num_tb) ? b_first + a.rr : a.num_tb;
     const int kg0 = gc * a.ct;
     const int kg1 = (kg0 + a.ct < a.num_tiles) ? kg0 + a.ct : a.num_tiles;
-    const int64_t stride = a.rows_pad;
-    double *pc = a.pcol + int64_t(gr) * 3 * stride;
+    // this workgroup's slot: row sums of rows b_first * TB.., column sums of sources kg0 * TS..
+    const int64_t stride = a.ge;
+    const int jb = kg0 * TS, rb0 = b_first * TB;
+    double *pc = a.scol + int64_t(blockIdx.x) * 3 * stride;
     if (a.sym) {
-        const int kend = KT * a.eblk[b_stop - 1];
-        if (kg0 >= (kend < a.num_tiles ? kend : a.num_tiles))
-            return;  // no block of the row group reaches this column group
-        // this workgroup alone writes the column sums of its tiles for its row group
         for (int k = kg0; k < kg1; ++k) {
-            const int j = k * TS + tid;
+            const int j = k * TS + tid - jb;
             pc[j] = 0.0;
             if (GRAD) {
                 pc[stride + j] = 0.0;
@@ -993,7 +1060,7 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
 
             if (cols) {
                 // owner lane of source tid: the four waves' sums in a fixed order
-                const int j = k * TS + tid;
+                const int j = k * TS + tid - jb;
                 double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
                 for (int w = 0; w < NW; ++w) {
@@ -1013,13 +1080,13 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
         }
 
         // this block's row sums against the column group, in the sums' natural units
-        double *out = a.prow + int64_t(gc) * 6 * stride;
+        double *out = a.srow + int64_t(blockIdx.x) * 6 * stride;
 #pragma unroll
         for (int q = 0; q < KT; ++q) {
             const int i = i0 + tid + q * WG;
             if (i >= iend)
                 continue;
-            const int rr = i - a.row_begin;
+            const int rr = i - a.row_begin - rb0;
             const double ce = a.out_exp;
             out[0 * stride + rr] = acc[q][0] * ce;
             out[3 * stride + rr] = acc[q][3] * ce;
@@ -1058,9 +1125,11 @@ struct PairBatchF32 {
     const int *g;
     const double *tile;
     const int *sblk, *eblk;
-    double *prow, *pcol;
+    CellMap cells;
+    double *srow, *scol;  // slots as in PairF32
+    int ge;
     int row_begin, row_end, rows_pad, num_tiles, num_tb;
-    int rr, ct, num_gr, num_gc;
+    int rr, ct;
     int sym, window, trig_cull;
     int theta_stride;
     const unsigned long long *umax;
@@ -1084,22 +1153,21 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32_batch(PairBatchF32
     __shared__ float lcol[2][NT][NW][TS];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15;
-    const int gr = a.num_gr - 1 - int(blockIdx.x / unsigned(a.num_gc));
-    const int gc = int(blockIdx.x % unsigned(a.num_gc));
+    int gr, gc;
+    if (!map_cell(a.cells, blockIdx.x, gr, gc))
+        return;
     const int b_first = gr * a.rr;
     const int b_stop = (b_first + a.rr < a.num_tb) ? b_first + a.rr : a.num_tb;
     const int kg0 = gc * a.ct;
     const int kg1 = (kg0 + a.ct < a.num_tiles) ? kg0 + a.ct : a.num_tiles;
-    const int64_t stride = a.rows_pad;
-    double *pc = a.pcol + int64_t(gr) * 3 * stride;
+    const int64_t stride = a.ge;
+    const int jb = kg0 * TS, rb0 = b_first * TB;
+    double *pc = a.scol + int64_t(blockIdx.x) * 3 * stride;
     if (a.sym) {
-        const int kend = KT * a.eblk[b_stop - 1];
-        if (kg0 >= (kend < a.num_tiles ? kend : a.num_tiles))
-            return;
         for (int k = kg0; k < kg1; ++k)
 #pragma unroll
             for (int z = 0; z < NT; ++z)
-                pc[z * stride + k * TS + tid] = 0.0;
+                pc[z * stride + k * TS + tid - jb] = 0.0;
     }
 
     auto stage = [&](int k, int buf) {
@@ -1425,7 +1493,7 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32_batch(PairBatchF32
             __syncthreads();
 
             if (cols) {
-                const int j = k * TS + tid;
+                const int j = k * TS + tid - jb;
 #pragma unroll
                 for (int z = 0; z < NT; ++z) {
                     double s = 0.0;
@@ -1437,13 +1505,13 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32_batch(PairBatchF32
             }
         }
 
-        double *out = a.prow + int64_t(gc) * 6 * stride;
+        double *out = a.srow + int64_t(blockIdx.x) * 6 * stride;
 #pragma unroll
         for (int q = 0; q < KT; ++q) {
             const int i = i0 + tid + q * WG;
             if (i >= iend)
                 continue;
-            const int rr = i - a.row_begin;
+            const int rr = i - a.row_begin - rb0;
 #pragma unroll
             for (int z = 0; z < NT; ++z) {
                 out[z * stride + rr] = acc[q][z][0] * a.out_exp;
@@ -1489,13 +1557,15 @@ __global__ __launch_bounds__(256) void k_sym_bounds(const double *__restrict__ t
     eblk[b] = int(lo);
 }
 
-// Which partial slots hold a row's sums in the symmetric sweep (one
-// workgroup): row group gr has row partials from column groups 0..gchi[gr]
-// (the workgroups that did not exit), and column group gc receives column
-// partials from row groups g0[gc]..num_gr-1.
+// Cells of the symmetric sweep (one workgroup): row group gr reaches column
+// groups 0..gchi[gr] (nondecreasing in gr), its cells are numbered from
+// rowstart[gr] on (latest row groups first: rowstart[num_gr - 1] = 0),
+// column group gc is reached by row groups g0[gc]..num_gr-1, and *total is
+// the number of cells.
 __global__ __launch_bounds__(256) void k_sym_plan(const int *__restrict__ eblk, int64_t num_tb, int64_t num_tiles,
                                                   int rr, int ct, int num_gr, int num_gc, int *__restrict__ gchi,
-                                                  int *__restrict__ g0)
+                                                  int *__restrict__ g0, int *__restrict__ rowstart,
+                                                  int *__restrict__ total)
 {
     __shared__ int hi[MAX_SYM_GROUPS];
     for (int g = threadIdx.x; g < num_gr; g += blockDim.x) {
@@ -1512,6 +1582,141 @@ __global__ __launch_bounds__(256) void k_sym_plan(const int *__restrict__ eblk, 
             ++g;
         g0[c] = g;
     }
+    if (threadIdx.x == 0) {
+        int start = 0;
+        for (int g = num_gr - 1; g >= 0; --g) {
+            rowstart[g] = start;
+            start += hi[g] + 1;
+        }
+        *total = start;
+    }
+}
+
+// Per-row accumulators cleared before the first pass (a kernel rather than a
+// memset node, so that callers may capture the call in a graph).
+__global__ __launch_bounds__(256) void k_zero(double *__restrict__ p, int64_t count)
+{
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i < count)
+        p[i] = 0.0;
+}
+
+// Fold of one pass: adds the slots of the pass's cells into the per-row FP64
+// accumulators, cell by cell in their launch order, so that the sums (and so
+// the results) do not depend on where passes begin and end.  Row sums of row
+// r come from the cells of its row group (column groups from the earliest
+// up); in the symmetric sweep its column sums come from the cells of its
+// column group (row groups from the latest down).
+struct FoldArgs {
+    CellMap m;
+    const int *g0;            // symmetric sweep: first row group reaching each column group
+    int ncells;               // cells of this pass: m.cell0 .. m.cell0 + ncells - 1
+    int rr, ct, ge, sym;
+    int rowmask, colmask;     // which of the 6 row and 3 column sums the sweep wrote
+    int64_t rows, rows_pad;
+    const double *srow, *scol;
+    double *acc_row, *acc_col;  // [6][rows_pad], [3][rows_pad]
+};
+
+// Cells of pass [c0, c1) that hold row sums of row r: row group gr, cells
+// [lo, hi) (empty if lo >= hi).
+__host__ __device__ inline void fold_row_cells(const CellMap &m, bool sym, int rr, int64_t r, int c0, int c1,
+                                               int &gr, int &lo, int &hi)
+{
+    gr = int((r / TB) / rr);
+    int rs, nc;
+    if (sym) {
+        rs = m.rowstart[gr];
+        nc = m.gchi[gr] + 1;
+    } else {
+        rs = (m.num_gr - 1 - gr) * m.num_gc;
+        nc = m.num_gc;
+    }
+    lo = rs > c0 ? rs : c0;
+    hi = (rs + nc < c1) ? rs + nc : c1;
+}
+
+// Symmetric sweep: cells of pass [c0, c1) that hold column sums of source r:
+// column group gc, row groups g from gmax down to gmin (cell rowstart[g] + gc,
+// which decreases with g; empty if gmin > gmax).
+__host__ __device__ inline void fold_col_cells(const CellMap &m, const int *g0, int ct, int64_t r, int c0, int c1,
+                                               int &gc, int &gmin, int &gmax)
+{
+    gc = int((r / TS) / ct);
+    const int gfirst = g0[gc];
+    int lo = gfirst, hi = m.num_gr;  // first g whose cell comes before c0
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (m.rowstart[mid] + gc < c0)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    gmax = lo - 1;
+    lo = gfirst;
+    hi = m.num_gr;  // first g whose cell comes before c1
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (m.rowstart[mid] + gc < c1)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    gmin = lo;
+}
+
+__global__ __launch_bounds__(256) void k_fold(FoldArgs a)
+{
+    const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (r >= a.rows)
+        return;
+    const int c0 = a.m.cell0, c1 = c0 + a.ncells;
+    if (a.sym && c0 >= *a.m.total)
+        return;
+    {
+        int gr, lo, hi;
+        fold_row_cells(a.m, a.sym != 0, a.rr, r, c0, c1, gr, lo, hi);
+        if (lo < hi) {
+            const int64_t rel = r - int64_t(gr) * a.rr * TB;
+            double v[6];
+#pragma unroll
+            for (int z = 0; z < 6; ++z)
+                v[z] = ((a.rowmask >> z) & 1) ? a.acc_row[z * a.rows_pad + r] : 0.0;
+            for (int c = lo; c < hi; ++c) {
+                const double *p = a.srow + int64_t(c - c0) * 6 * a.ge + rel;
+#pragma unroll
+                for (int z = 0; z < 6; ++z)
+                    if ((a.rowmask >> z) & 1)
+                        v[z] += p[z * a.ge];
+            }
+#pragma unroll
+            for (int z = 0; z < 6; ++z)
+                if ((a.rowmask >> z) & 1)
+                    a.acc_row[z * a.rows_pad + r] = v[z];
+        }
+    }
+    if (a.sym && a.colmask) {
+        int gc, gmin, gmax;
+        fold_col_cells(a.m, a.g0, a.ct, r, c0, c1, gc, gmin, gmax);
+        if (gmin <= gmax) {
+            const int64_t rel = r - int64_t(gc) * a.ct * TS;
+            double v[3];
+#pragma unroll
+            for (int z = 0; z < 3; ++z)
+                v[z] = ((a.colmask >> z) & 1) ? a.acc_col[z * a.rows_pad + r] : 0.0;
+            for (int g = gmax; g >= gmin; --g) {
+                const double *p = a.scol + int64_t(a.m.rowstart[g] + gc - c0) * 3 * a.ge + rel;
+#pragma unroll
+                for (int z = 0; z < 3; ++z)
+                    if ((a.colmask >> z) & 1)
+                        v[z] += p[z * a.ge];
+            }
+#pragma unroll
+            for (int z = 0; z < 3; ++z)
+                if ((a.colmask >> z) & 1)
+                    a.acc_col[z * a.rows_pad + r] = v[z];
+        }
+    }
 }
 
 struct PairF64 {
@@ -1519,9 +1724,11 @@ struct PairF64 {
     const int *g;
     const double *tile;
     const int *sblk, *eblk;  // symmetric sweep: block order bounds (as in PairF32)
-    double *prow, *pcol;     // row partials [num_gc][6][rows_pad], column partials [num_gr][3][rows_pad]
+    CellMap cells;
+    double *srow, *scol;     // slots as in PairF32
+    int ge;
     int n, row_begin, row_end, rows_pad, num_tiles, num_tb;
-    int rr, ct, num_gr, num_gc, sym;
+    int rr, ct, sym;
     double ax, at, qh, omega;  // log2(e) times: 1/(2 tau_x^2), 1/(2 tau_t^2), 1/(2 h0^2), omega
 };
 
@@ -1580,20 +1787,19 @@ __global__ __launch_bounds__(WG) void k_pair_f64(PairF64 a)
     __shared__ double lcol[3][NW][TS];  // per-wave column sums of the tile just swept
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15;
-    const int gr = a.num_gr - 1 - int(blockIdx.x / unsigned(a.num_gc));  // latest row groups first
-    const int gc = int(blockIdx.x % unsigned(a.num_gc));
+    int gr, gc;
+    if (!map_cell(a.cells, blockIdx.x, gr, gc))
+        return;
     const int b_first = gr * a.rr;
     const int b_stop = (b_first + a.rr < a.num_tb) ? b_first + a.rr : a.num_tb;
     const int kg0 = gc * a.ct;
     const int kg1 = (kg0 + a.ct < a.num_tiles) ? kg0 + a.ct : a.num_tiles;
-    const int64_t stride = a.rows_pad;
-    double *pc = a.pcol + int64_t(gr) * 3 * stride;
+    const int64_t stride = a.ge;
+    const int jb = kg0 * TS, rb0 = b_first * TB;
+    double *pc = a.scol + int64_t(blockIdx.x) * 3 * stride;
     if (a.sym) {
-        const int kend = KT * a.eblk[b_stop - 1];
-        if (kg0 >= (kend < a.num_tiles ? kend : a.num_tiles))
-            return;  // no block of the row group reaches this column group
         for (int k = kg0; k < kg1; ++k) {
-            const int j = k * TS + tid;
+            const int j = k * TS + tid - jb;
             pc[j] = 0.0;
             if (GRAD) {
                 pc[stride + j] = 0.0;
@@ -1762,7 +1968,7 @@ __global__ __launch_bounds__(WG) void k_pair_f64(PairF64 a)
             __syncthreads();
             if (cols) {
                 // owner lane of source tid: the four waves' sums in a fixed order
-                const int j = k * TS + tid;
+                const int j = k * TS + tid - jb;
                 double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
                 for (int w = 0; w < NW; ++w) {
@@ -1781,13 +1987,13 @@ __global__ __launch_bounds__(WG) void k_pair_f64(PairF64 a)
             }
         }
 
-        double *out = a.prow + int64_t(gc) * 6 * stride;
+        double *out = a.srow + int64_t(blockIdx.x) * 6 * stride;
 #pragma unroll
         for (int q = 0; q < KT; ++q) {
             const int i = i0 + tid + q * WG;
             if (i >= iend)
                 continue;
-            const int rr = i - a.row_begin;
+            const int rr = i - a.row_begin - rb0;
             out[0 * stride + rr] = acc[q][0];
             out[3 * stride + rr] = acc[q][3];
             if (GRAD) {
@@ -1803,15 +2009,14 @@ __global__ __launch_bounds__(WG) void k_pair_f64(PairF64 a)
 struct Fin {
     const double *t, *x, *y, *s;   // raw events (the rescue sweep reads them)
     const int *g;                  // tie-group ids
-    const double *partials;        // row partials [slot][6][rows_pad]
-    const double *pcol;            // symmetric sweep: column partials [row group][3][rows_pad]
-    const int *gchi, *g0;          // symmetric sweep: partial slots of each row and column group
+    const double *acc_row;         // folded row sums [6][rows_pad]
+    const double *acc_col;         // symmetric sweep: folded column sums [3][rows_pad]
     int *status;                   // [0] flags, [1] rescue count
     int *rescue;                   // rescue list of row offsets
     double *rowvals;               // [7][rows_cap] per-row l_n and gradient terms
     double *lam_out, *comp_out;
-    int64_t n, row_begin, rows, rows_pad, rows_cap, num_chunks;  // num_chunks: row sweep slots
-    int sym, rr, ct, num_gr;
+    int64_t n, row_begin, rows, rows_pad, rows_cap;
+    int sym;
     double mu, tau_x, tau_t, xi, h0, omega, c_b, c_g;
     double ax, at, qh;             // 1/(2 tau_x^2), 1/(2 tau_t^2), 1/(2 h0^2)
     double rescue_lambda;          // FP32 rows with lambda below this are recomputed (0: never)
@@ -1858,11 +2063,9 @@ __device__ void row_terms(const Fin &f, const double S[6], double ti, double tN,
     }
 }
 
-// Per-row FP64 finalize: sums the partials in a fixed order, then
-// lambda_n, the floored log, gradient terms and the compensator.  Row sweep:
-// every chunk slot.  Symmetric sweep: the row partials of the column groups
-// the row's group reached, then the column partials of the row groups that
-// reached the row's column group.
+// Per-row FP64 finalize: the row's folded sums (row sums, plus in the
+// symmetric sweep the background column sums), then lambda_n, the floored
+// log, gradient terms and the compensator.
 template <bool GRAD>
 __global__ __launch_bounds__(256) void k_finalize(Fin f)
 {
@@ -1870,27 +2073,21 @@ __global__ __launch_bounds__(256) void k_finalize(Fin f)
     if (r >= f.rows)
         return;
     double S[6] = {0, 0, 0, 0, 0, 0};
-    const int64_t nslot = f.sym ? int64_t(f.gchi[(r / TB) / f.rr]) + 1 : f.num_chunks;
-    for (int64_t c = 0; c < nslot; ++c) {
-        const double *p = f.partials + c * 6 * f.rows_pad + r;
-        S[0] += p[0];
-        S[3] += p[3 * f.rows_pad];
+    S[0] = f.acc_row[r];
+    S[3] = f.acc_row[3 * f.rows_pad + r];
+    if (GRAD) {
+        S[1] = f.acc_row[1 * f.rows_pad + r];
+        S[2] = f.acc_row[2 * f.rows_pad + r];
+        S[4] = f.acc_row[4 * f.rows_pad + r];
+        S[5] = f.acc_row[5 * f.rows_pad + r];
+    }
+    if (f.sym) {
+        S[0] += f.acc_col[r];
         if (GRAD) {
-            S[1] += p[1 * f.rows_pad];
-            S[2] += p[2 * f.rows_pad];
-            S[4] += p[4 * f.rows_pad];
-            S[5] += p[5 * f.rows_pad];
+            S[1] += f.acc_col[1 * f.rows_pad + r];
+            S[2] += f.acc_col[2 * f.rows_pad + r];
         }
     }
-    if (f.sym)
-        for (int64_t g = f.g0[(r / TS) / f.ct]; g < f.num_gr; ++g) {
-            const double *p = f.pcol + g * 3 * f.rows_pad + r;
-            S[0] += p[0];
-            if (GRAD) {
-                S[1] += p[1 * f.rows_pad];
-                S[2] += p[2 * f.rows_pad];
-            }
-        }
     const int64_t i = f.row_begin + r;
     double v[7] = {0, 0, 0, 0, 0, 0, 0}, lam, comp;
     row_terms<GRAD>(f, S, f.t[i], f.t[f.n - 1], v, lam, comp);
@@ -2038,9 +2235,44 @@ __global__ void k_poison_rows(const int *status, double *lam, double *comp, int6
 
 thread_local char g_errbuf[512];
 
-bool g_timing = false;
-hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
-bool g_timing_recorded = false;
+// Per-call tuning and timing (hawkes_options; defaults when absent).
+struct Tuning {
+    int64_t row_wgs = DEFAULT_ROW_WGS;
+    int sym_groups = DEFAULT_SYM_GROUPS;  // 0: whole-set calls take the row sweep
+    hipEvent_t t_start = nullptr, t_stop = nullptr;
+};
+
+int parse_options(const hawkes_options *o, Tuning &T)
+{
+    if (!o)
+        return HAWKES_OK;
+    if (o->row_workgroups != 0) {
+        if (o->row_workgroups < 1 || o->row_workgroups > MAX_ROW_WGS) {
+            set_error("row_workgroups %lld outside [1, %lld]", (long long)o->row_workgroups,
+                      (long long)MAX_ROW_WGS);
+            return HAWKES_EINVAL;
+        }
+        T.row_wgs = o->row_workgroups;
+    }
+    if (o->symmetric_groups != 0) {
+        if (o->symmetric_groups < -1 || o->symmetric_groups > MAX_SYM_GROUPS) {
+            set_error("symmetric_groups %d outside [-1, %d]", int(o->symmetric_groups), MAX_SYM_GROUPS);
+            return HAWKES_EINVAL;
+        }
+        T.sym_groups = o->symmetric_groups < 0 ? 0 : int(o->symmetric_groups);
+    }
+    if (o->reserved != 0) {
+        set_error("hawkes_options.reserved must be 0");
+        return HAWKES_EINVAL;
+    }
+    if ((o->timing_start == nullptr) != (o->timing_stop == nullptr)) {
+        set_error("timing_start and timing_stop must both be set or both be NULL");
+        return HAWKES_EINVAL;
+    }
+    T.t_start = reinterpret_cast<hipEvent_t>(o->timing_start);
+    T.t_stop = reinterpret_cast<hipEvent_t>(o->timing_stop);
+    return HAWKES_OK;
+}
 
 int validate(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t rb, int64_t re, const void *ws,
              size_t ws_bytes, Layout *L)
@@ -2076,8 +2308,9 @@ int validate(const hawkes_events *ev, const hawkes_theta *th, int precision, int
         return HAWKES_ERANGE;
     }
     *L = make_layout(ev->n, precision);
-    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0 || ws_bytes < L->total) {
-        set_error("workspace %p of %zu bytes; need %zu bytes, 256-byte aligned", ws, ws_bytes, L->total);
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0 || ws_bytes < L->minimum) {
+        set_error("workspace %p of %zu bytes; need at least %zu bytes (%zu recommended), 256-byte aligned", ws,
+                  ws_bytes, L->minimum, L->total);
         return HAWKES_EWORKSPACE;
     }
     return HAWKES_OK;
@@ -2098,20 +2331,26 @@ T *at(void *ws, size_t off)
 enum Mode { MODE_LOGLIK, MODE_GRAD, MODE_TERMS };
 
 // What every call stages before its pair sweep: tie groups, tile time ranges
-// and data checks; the work plan; for the symmetric sweep its block bounds.
+// and data checks; the work plan (cells and passes); for the symmetric sweep
+// its block bounds and cell numbering.
 struct Setup {
     Plan P;
     SymPlan SP;
     bool sym = false, uniform = false;
-    int grid_rr = 1, grid_ct = 1, grid_gr = 0, grid_gc = 0;
-    unsigned pair_blocks = 0, stage_blocks = 0;
+    int grid_rr = 1, grid_ct = 1;
+    unsigned stage_blocks = 0;
     int64_t n = 0, rb = 0, re = 0, rows = 0;
-    int *status = nullptr, *g = nullptr, *sblk = nullptr, *eblk = nullptr;
-    double *tile = nullptr, *partials = nullptr, *pcol = nullptr;
+    int *status = nullptr, *g = nullptr, *sblk = nullptr, *eblk = nullptr, *g0 = nullptr;
+    double *tile = nullptr, *acc_row = nullptr, *acc_col = nullptr;
+    CellMap cells;
+    int ge = TB;
+    size_t cell_bytes = 0, slot_avail = 0;
+    int64_t cells_ub = 0, cap = 0, passes = 0;
+    double *srow = nullptr, *scol = nullptr;
 };
 
-int setup(const hawkes_events *ev, int64_t rb, int64_t re, void *ws, const Layout &L, hipStream_t stream,
-          Setup &S)
+int setup(const hawkes_events *ev, int64_t rb, int64_t re, void *ws, size_t ws_bytes, const Layout &L,
+          const Tuning &T, hipStream_t stream, Setup &S)
 {
     int rc;
     S.n = ev->n;
@@ -2124,7 +2363,20 @@ int setup(const hawkes_events *ev, int64_t rb, int64_t re, void *ws, const Layou
     S.tile = at<double>(ws, L.tile);
     S.sblk = at<int>(ws, L.sblk);
     S.eblk = at<int>(ws, L.eblk);
-    S.partials = at<double>(ws, L.partials);
+    S.g0 = at<int>(ws, L.g0);
+
+    // the plan, and whether one cell's slot fits, before any work is enqueued
+    S.P = make_plan(S.rows > 0 ? S.rows : 1, L.num_tiles, T.row_wgs);
+    // the symmetric sweep covers the whole event set; a row range takes the row sweep
+    S.sym = T.sym_groups > 0 && rb == 0 && re == S.n;
+    S.SP = S.sym ? make_sym_plan(S.P.num_tb, L.num_tiles, T.sym_groups) : SymPlan{};
+    S.cell_bytes = S.sym ? sym_cell_bytes(S.SP) : row_cell_bytes();
+    S.slot_avail = ws_bytes - L.slots;
+    if (S.slot_avail < S.cell_bytes) {
+        set_error("workspace of %zu bytes leaves %zu bytes of slots; one cell of this plan needs %zu", ws_bytes,
+                  S.slot_avail, S.cell_bytes);
+        return HAWKES_EWORKSPACE;
+    }
 
     hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, stream, S.status);
     S.stage_blocks = unsigned(ceil_div(L.n_pad, 256));
@@ -2133,27 +2385,110 @@ int setup(const hawkes_events *ev, int64_t rb, int64_t re, void *ws, const Layou
     if ((rc = check_launch("stage_common")) != HAWKES_OK || S.rows == 0)
         return rc;
 
-    S.P = make_plan(S.rows, L.num_tiles);
-    // the symmetric sweep covers the whole event set; a row range takes the row sweep
-    S.sym = g_sym_groups > 0 && rb == 0 && re == S.n;
-    S.SP = S.sym ? make_sym_plan(S.P.num_tb, L.num_tiles, g_sym_groups) : SymPlan{};
+    int *rowstart = at<int>(ws, L.rowstart);
     if (S.sym) {
         hipLaunchKernelGGL(k_sym_bounds, dim3(unsigned(ceil_div(S.P.num_tb, 256))), dim3(256), 0, stream, ev->t,
                            S.n, S.P.num_tb, S.sblk, S.eblk);
         if ((rc = check_launch("sym_bounds")) != HAWKES_OK)
             return rc;
         hipLaunchKernelGGL(k_sym_plan, dim3(1), dim3(256), 0, stream, S.eblk, S.P.num_tb, L.num_tiles, S.SP.rr,
-                           S.SP.ct, S.SP.num_gr, S.SP.num_gc, at<int>(ws, L.gchi), at<int>(ws, L.g0));
+                           S.SP.ct, S.SP.num_gr, S.SP.num_gc, at<int>(ws, L.gchi), S.g0, rowstart,
+                           rowstart + MAX_SYM_GROUPS);
         if ((rc = check_launch("sym_plan")) != HAWKES_OK)
             return rc;
     }
-    // row groups x column groups of the sweep: the symmetric plan, or target blocks x source chunks
+    // cells: row groups x column groups (the symmetric plan), or target blocks x source chunks
     S.grid_rr = S.sym ? S.SP.rr : 1;
     S.grid_ct = S.sym ? S.SP.ct : int(S.P.chunk_tiles);
-    S.grid_gr = S.sym ? S.SP.num_gr : int(S.P.num_tb);
-    S.grid_gc = S.sym ? S.SP.num_gc : int(S.P.num_chunks);
-    S.pair_blocks = unsigned(int64_t(S.grid_gr) * S.grid_gc);
-    S.pcol = S.partials + int64_t(S.SP.num_gc) * 6 * S.P.rows_pad;
+    S.cells.num_gr = S.sym ? S.SP.num_gr : int(S.P.num_tb);
+    S.cells.num_gc = S.sym ? S.SP.num_gc : int(S.P.num_chunks);
+    if (S.sym) {
+        S.cells.rowstart = rowstart;
+        S.cells.gchi = at<int>(ws, L.gchi);
+        S.cells.total = rowstart + MAX_SYM_GROUPS;
+    }
+    S.ge = S.sym ? S.SP.rr * TB : TB;
+    S.cells_ub = int64_t(S.cells.num_gr) * S.cells.num_gc;
+    S.acc_row = at<double>(ws, L.acc);
+    S.acc_col = S.acc_row + 6 * S.P.rows_pad;
+    S.srow = at<double>(ws, L.slots);
+    return HAWKES_OK;
+}
+
+// Workgroups of `kernel` the device runs at once (0 if unknown).
+int device_concurrency(const void *kernel)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, WG, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return cus * per_cu;
+}
+
+// Pass plan: as many cells per pass as the slot region holds, rounded down to
+// whole rounds of the workgroups the device runs at once (so that a pass ends
+// without a ragged round of its own).
+void plan_passes(Setup &S, const void *kernel)
+{
+    int64_t cap = int64_t(S.slot_avail / S.cell_bytes);
+    if (cap >= S.cells_ub)
+        cap = S.cells_ub;
+    else {
+        const int64_t conc = device_concurrency(kernel);
+        if (conc > 0 && cap > conc)
+            cap -= cap % conc;
+    }
+    S.cap = cap;
+    S.passes = ceil_div(S.cells_ub, cap);
+    S.scol = S.srow + cap * 6 * S.ge;  // symmetric sweep: column slots after the row slots
+}
+
+// Runs the sweep pass by pass: clears the accumulators, then for each pass
+// launches the pair kernel over its cells (launch(cell0, grid)) and folds the
+// slots.  The caller's timing events bracket the passes.
+template <typename Launch>
+int sweep_passes(const Setup &S, const Tuning &T, int rowmask, int colmask, hipStream_t stream, Launch launch)
+{
+    int rc;
+    const int64_t acc_count = 9 * S.P.rows_pad;
+    hipLaunchKernelGGL(k_zero, dim3(unsigned(ceil_div(acc_count, 256))), dim3(256), 0, stream, S.acc_row,
+                       acc_count);
+    if ((rc = check_launch("zero")) != HAWKES_OK)
+        return rc;
+    if (T.t_start && (rc = record_event(T.t_start, stream)) != HAWKES_OK)
+        return rc;
+    FoldArgs fa;
+    fa.m = S.cells;
+    fa.g0 = S.g0;
+    fa.rr = S.grid_rr;
+    fa.ct = S.grid_ct;
+    fa.ge = S.ge;
+    fa.sym = S.sym ? 1 : 0;
+    fa.rowmask = rowmask;
+    fa.colmask = S.sym ? colmask : 0;
+    fa.rows = S.rows;
+    fa.rows_pad = S.P.rows_pad;
+    fa.srow = S.srow;
+    fa.scol = S.scol;
+    fa.acc_row = S.acc_row;
+    fa.acc_col = S.acc_col;
+    for (int64_t p = 0; p < S.passes; ++p) {
+        const int64_t cell0 = p * S.cap;
+        const int64_t grid = (S.cells_ub - cell0 < S.cap) ? S.cells_ub - cell0 : S.cap;
+        launch(int(cell0), unsigned(grid));
+        if ((rc = check_launch("pair sweep")) != HAWKES_OK)
+            return rc;
+        fa.m.cell0 = int(cell0);
+        fa.ncells = int(grid);
+        hipLaunchKernelGGL(k_fold, dim3(unsigned(ceil_div(S.rows, 256))), dim3(256), 0, stream, fa);
+        if ((rc = check_launch("fold")) != HAWKES_OK)
+            return rc;
+    }
+    if (T.t_stop && (rc = record_event(T.t_stop, stream)) != HAWKES_OK)
+        return rc;
     return HAWKES_OK;
 }
 
@@ -2171,15 +2506,17 @@ StageF32 stage_scales(const hawkes_theta *th, bool uniform)
     return sc;
 }
 
-// The sweep's grid and partial-sum fields shared by the FP32 kernels.
+// The sweep's cell and slot fields shared by the pair kernels.
 template <typename A>
 void fill_grid(A &a, const Setup &S, const Layout &L)
 {
     a.tile = S.tile;
     a.sblk = S.sblk;
     a.eblk = S.eblk;
-    a.prow = S.partials;
-    a.pcol = S.pcol;
+    a.cells = S.cells;
+    a.srow = S.srow;
+    a.scol = S.scol;
+    a.ge = S.ge;
     a.row_begin = int(S.rb);
     a.row_end = int(S.re);
     a.rows_pad = int(S.P.rows_pad);
@@ -2187,8 +2524,6 @@ void fill_grid(A &a, const Setup &S, const Layout &L)
     a.num_tb = int(S.P.num_tb);
     a.rr = S.grid_rr;
     a.ct = S.grid_ct;
-    a.num_gr = S.grid_gr;
-    a.num_gc = S.grid_gc;
     a.sym = S.sym ? 1 : 0;
 }
 
@@ -2202,7 +2537,8 @@ Fin make_fin(const hawkes_events *ev, const hawkes_theta *th, int precision, con
     f.y = ev->y;
     f.s = ev->s;
     f.g = S.g;
-    f.partials = S.partials;
+    f.acc_row = S.acc_row;
+    f.acc_col = S.acc_col;
     f.status = S.status;
     f.rescue = at<int>(ws, L.rescue);
     f.rowvals = at<double>(ws, L.rowvals);
@@ -2213,14 +2549,7 @@ Fin make_fin(const hawkes_events *ev, const hawkes_theta *th, int precision, con
     f.rows = S.rows;
     f.rows_pad = S.P.rows_pad;
     f.rows_cap = L.rows_cap;
-    f.num_chunks = S.P.num_chunks;
     f.sym = S.sym ? 1 : 0;
-    f.rr = S.SP.rr;
-    f.ct = S.SP.ct;
-    f.num_gr = S.SP.num_gr;
-    f.pcol = S.pcol;
-    f.gchi = at<int>(ws, L.gchi);
-    f.g0 = at<int>(ws, L.g0);
     f.mu = th->mu;
     f.tau_x = tau_x;
     f.tau_t = tau_t;
@@ -2289,11 +2618,15 @@ int finish(const Fin &f, const Setup &S, const Layout &L, void *ws, int precisio
 }
 
 int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t rb, int64_t re, void *ws,
-        size_t ws_bytes, double *d_loglik, double *d_grad, double *d_lam, double *d_comp, Mode mode, void *stream_)
+        size_t ws_bytes, const hawkes_options *opts, double *d_loglik, double *d_grad, double *d_lam,
+        double *d_comp, Mode mode, void *stream_)
 {
-    Layout L;
-    int rc = validate(ev, th, precision, rb, re, ws, ws_bytes, &L);
+    Tuning T;
+    int rc = parse_options(opts, T);
     if (rc != HAWKES_OK)
+        return rc;
+    Layout L;
+    if ((rc = validate(ev, th, precision, rb, re, ws, ws_bytes, &L)) != HAWKES_OK)
         return rc;
     if (mode != MODE_TERMS && !d_loglik) {
         set_error("null loglik output");
@@ -2306,7 +2639,7 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
     hipStream_t stream = as_stream(stream_);
     const bool grad = (mode == MODE_GRAD);
     Setup S;
-    if ((rc = setup(ev, rb, re, ws, L, stream, S)) != HAWKES_OK)
+    if ((rc = setup(ev, rb, re, ws, ws_bytes, L, T, stream, S)) != HAWKES_OK)
         return rc;
     if (S.rows == 0) {
         if (mode != MODE_TERMS)
@@ -2315,6 +2648,8 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
     }
     const double h0 = th->h0, omega = th->omega;
     const bool uniform = S.uniform;
+    // row sums written by the sweeps: all six with the gradient, S0 and G0 without
+    const int rowmask = grad ? 0x3F : 0x09, colmask = grad ? 0x7 : 0x1;
 
     if (is_fp32(precision)) {
         const StageF32 sc = stage_scales(th, uniform);
@@ -2325,6 +2660,11 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
                            S.g, S.n, L.n_pad, sc, S.tile, xs, ys, tsd, r2, v2, u2, dg);
         if ((rc = check_launch("stage_f32")) != HAWKES_OK)
             return rc;
+        const void *kfn = grad ? (uniform ? reinterpret_cast<const void *>(&k_pair_f32<true, true>)
+                                          : reinterpret_cast<const void *>(&k_pair_f32<true, false>))
+                               : (uniform ? reinterpret_cast<const void *>(&k_pair_f32<false, true>)
+                                          : reinterpret_cast<const void *>(&k_pair_f32<false, false>));
+        plan_passes(S, kfn);
         PairF32 a;
         fill_grid(a, S, L);
         a.xs = xs;
@@ -2358,25 +2698,23 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
             a.window = 0;
             a.trig_cull = 0;
         }
-        if (g_timing && (rc = record_event(g_ev_start, stream)) != HAWKES_OK)
-            return rc;
-        const dim3 grid(S.pair_blocks);
-        if (grad && uniform)
-            hipLaunchKernelGGL((k_pair_f32<true, true>), grid, dim3(WG), 0, stream, a);
-        else if (grad)
-            hipLaunchKernelGGL((k_pair_f32<true, false>), grid, dim3(WG), 0, stream, a);
-        else if (uniform)
-            hipLaunchKernelGGL((k_pair_f32<false, true>), grid, dim3(WG), 0, stream, a);
-        else
-            hipLaunchKernelGGL((k_pair_f32<false, false>), grid, dim3(WG), 0, stream, a);
-        if (g_timing) {
-            if ((rc = record_event(g_ev_stop, stream)) != HAWKES_OK)
-                return rc;
-            g_timing_recorded = true;
-        }
-        if ((rc = check_launch("pair_f32")) != HAWKES_OK)
+        rc = sweep_passes(S, T, rowmask, colmask, stream, [&](int cell0, unsigned grid) {
+            a.cells.cell0 = cell0;
+            if (grad && uniform)
+                hipLaunchKernelGGL((k_pair_f32<true, true>), dim3(grid), dim3(WG), 0, stream, a);
+            else if (grad)
+                hipLaunchKernelGGL((k_pair_f32<true, false>), dim3(grid), dim3(WG), 0, stream, a);
+            else if (uniform)
+                hipLaunchKernelGGL((k_pair_f32<false, true>), dim3(grid), dim3(WG), 0, stream, a);
+            else
+                hipLaunchKernelGGL((k_pair_f32<false, false>), dim3(grid), dim3(WG), 0, stream, a);
+        });
+        if (rc != HAWKES_OK)
             return rc;
     } else {
+        const void *kfn = grad ? reinterpret_cast<const void *>(&k_pair_f64<true>)
+                               : reinterpret_cast<const void *>(&k_pair_f64<false>);
+        plan_passes(S, kfn);
         PairF64 a;
         a.t = ev->t;
         a.x = ev->x;
@@ -2386,8 +2724,10 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
         a.tile = S.tile;
         a.sblk = S.sblk;
         a.eblk = S.eblk;
-        a.prow = S.partials;
-        a.pcol = S.pcol;
+        a.cells = S.cells;
+        a.srow = S.srow;
+        a.scol = S.scol;
+        a.ge = S.ge;
         a.n = int(S.n);
         a.row_begin = int(rb);
         a.row_end = int(re);
@@ -2396,26 +2736,20 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
         a.num_tb = int(S.P.num_tb);
         a.rr = S.grid_rr;
         a.ct = S.grid_ct;
-        a.num_gr = S.grid_gr;
-        a.num_gc = S.grid_gc;
         a.sym = S.sym ? 1 : 0;
         // exponents in units of log2 (the sweep's exp2); uniform background: no spatial factor
         a.ax = uniform ? 0.0 : LOG2E / (2.0 * th->tau_x * th->tau_x);
         a.at = LOG2E / (2.0 * th->tau_t * th->tau_t);
         a.qh = LOG2E / (2.0 * h0 * h0);
         a.omega = omega * LOG2E;
-        if (g_timing && (rc = record_event(g_ev_start, stream)) != HAWKES_OK)
-            return rc;
-        if (grad)
-            hipLaunchKernelGGL(k_pair_f64<true>, dim3(S.pair_blocks), dim3(WG), 0, stream, a);
-        else
-            hipLaunchKernelGGL(k_pair_f64<false>, dim3(S.pair_blocks), dim3(WG), 0, stream, a);
-        if (g_timing) {
-            if ((rc = record_event(g_ev_stop, stream)) != HAWKES_OK)
-                return rc;
-            g_timing_recorded = true;
-        }
-        if ((rc = check_launch("pair_f64")) != HAWKES_OK)
+        rc = sweep_passes(S, T, rowmask, colmask, stream, [&](int cell0, unsigned grid) {
+            a.cells.cell0 = cell0;
+            if (grad)
+                hipLaunchKernelGGL(k_pair_f64<true>, dim3(grid), dim3(WG), 0, stream, a);
+            else
+                hipLaunchKernelGGL(k_pair_f64<false>, dim3(grid), dim3(WG), 0, stream, a);
+        });
+        if (rc != HAWKES_OK)
             return rc;
     }
 
@@ -2427,7 +2761,7 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
 // vectors share one forward-only sweep (k_pair_f32_batch), a vector left over
 // takes the single sweep; FP64: one sweep per vector.
 int run_batch(const hawkes_events *ev, const hawkes_theta *th, int64_t num_theta, int precision, int64_t rb,
-              int64_t re, void *ws, size_t ws_bytes, double *d_loglik, void *stream_)
+              int64_t re, void *ws, size_t ws_bytes, const hawkes_options *opts, double *d_loglik, void *stream_)
 {
     if (!th || num_theta < 1) {
         set_error("need at least one theta (got %lld, pointer %p)", (long long)num_theta, (const void *)th);
@@ -2437,27 +2771,33 @@ int run_batch(const hawkes_events *ev, const hawkes_theta *th, int64_t num_theta
         set_error("null loglik output");
         return HAWKES_EINVAL;
     }
+    Tuning T;
+    int rc = parse_options(opts, T);
+    if (rc != HAWKES_OK)
+        return rc;
     Layout L;
-    int rc;
     for (int64_t k = 0; k < num_theta; ++k)
         if ((rc = validate(ev, th + k, precision, rb, re, ws, ws_bytes, &L)) != HAWKES_OK)
             return rc;
     if (!is_fp32(precision) || num_theta == 1 || re == rb) {
         for (int64_t k = 0; k < num_theta; ++k)
-            if ((rc = run(ev, th + k, precision, rb, re, ws, ws_bytes, d_loglik + k, nullptr, nullptr, nullptr,
-                          MODE_LOGLIK, stream_)) != HAWKES_OK)
+            if ((rc = run(ev, th + k, precision, rb, re, ws, ws_bytes, opts, d_loglik + k, nullptr, nullptr,
+                          nullptr, MODE_LOGLIK, stream_)) != HAWKES_OK)
                 return rc;
         return HAWKES_OK;
     }
     hipStream_t stream = as_stream(stream_);
     Setup S;
-    if ((rc = setup(ev, rb, re, ws, L, stream, S)) != HAWKES_OK)
+    if ((rc = setup(ev, rb, re, ws, ws_bytes, L, T, stream, S)) != HAWKES_OK)
         return rc;
     if (precision == HAWKES_FP32_SKIP) {
         hipLaunchKernelGGL(k_umax, dim3(unsigned(ceil_div(S.n, 256))), dim3(256), 0, stream, ev->s, S.n, S.status);
         if ((rc = check_launch("umax")) != HAWKES_OK)
             return rc;
     }
+    const void *kfn = S.uniform ? reinterpret_cast<const void *>(&k_pair_f32_batch<MAX_FUSED_THETA, true>)
+                                : reinterpret_cast<const void *>(&k_pair_f32_batch<MAX_FUSED_THETA, false>);
+    plan_passes(S, kfn);
     double *xs = at<double>(ws, L.xs), *ys = at<double>(ws, L.ys), *tsd = at<double>(ws, L.tsd);
     float2 *r2 = at<float2>(ws, L.r2), *v2 = at<float2>(ws, L.v2), *u2 = at<float2>(ws, L.u2);
     DeltaGroup *dg = at<DeltaGroup>(ws, L.dg);
@@ -2515,26 +2855,22 @@ int run_batch(const hawkes_events *ev, const hawkes_theta *th, int64_t num_theta
             a.window = 0;
             a.trig_cull = 0;
         }
-        if (g_timing && (rc = record_event(g_ev_start, stream)) != HAWKES_OK)
-            return rc;
-        if (S.uniform)
-            hipLaunchKernelGGL((k_pair_f32_batch<MAX_FUSED_THETA, true>), dim3(S.pair_blocks), dim3(WG), 0, stream,
-                               a);
-        else
-            hipLaunchKernelGGL((k_pair_f32_batch<MAX_FUSED_THETA, false>), dim3(S.pair_blocks), dim3(WG), 0,
-                               stream, a);
-        if (g_timing) {
-            if ((rc = record_event(g_ev_stop, stream)) != HAWKES_OK)
-                return rc;
-            g_timing_recorded = true;
-        }
-        if ((rc = check_launch("pair_f32_batch")) != HAWKES_OK)
+        // vector z's S0 and G0 go to row sums z and 3 + z, its column sums to z
+        rc = sweep_passes(S, T, 0x1B, 0x3, stream, [&](int cell0, unsigned grid) {
+            a.cells.cell0 = cell0;
+            if (S.uniform)
+                hipLaunchKernelGGL((k_pair_f32_batch<MAX_FUSED_THETA, true>), dim3(grid), dim3(WG), 0, stream, a);
+            else
+                hipLaunchKernelGGL((k_pair_f32_batch<MAX_FUSED_THETA, false>), dim3(grid), dim3(WG), 0, stream,
+                                   a);
+        });
+        if (rc != HAWKES_OK)
             return rc;
         for (int z = 0; z < MAX_FUSED_THETA; ++z) {
-            // vector z's sums sit z slots further on in the row and column partials
+            // vector z's sums sit z rows further on in the accumulators
             Fin f = make_fin(ev, t0 + z, precision, S, L, ws, nullptr, nullptr);
-            f.partials = S.partials + int64_t(z) * S.P.rows_pad;
-            f.pcol = S.pcol + int64_t(z) * S.P.rows_pad;
+            f.acc_row = S.acc_row + int64_t(z) * S.P.rows_pad;
+            f.acc_col = S.acc_col + int64_t(z) * S.P.rows_pad;
             hipLaunchKernelGGL(k_clear_rescue, dim3(1), dim3(1), 0, stream, S.status);
             if ((rc = check_launch("clear_rescue")) != HAWKES_OK)
                 return rc;
@@ -2544,13 +2880,14 @@ int run_batch(const hawkes_events *ev, const hawkes_theta *th, int64_t num_theta
         }
     }
     for (; k < num_theta; ++k)
-        if ((rc = run(ev, th + k, precision, rb, re, ws, ws_bytes, d_loglik + k, nullptr, nullptr, nullptr,
+        if ((rc = run(ev, th + k, precision, rb, re, ws, ws_bytes, opts, d_loglik + k, nullptr, nullptr, nullptr,
                       MODE_LOGLIK, stream_)) != HAWKES_OK)
             return rc;
     return HAWKES_OK;
 }
 
 }  // namespace
+
 
 void set_error(const char *fmt, ...)
 {
@@ -2585,35 +2922,43 @@ extern "C" size_t hawkes_workspace_bytes(int64_t n, int precision)
     return make_layout(n, precision).total;
 }
 
+extern "C" size_t hawkes_workspace_min_bytes(int64_t n, int precision)
+{
+    if (n < 1 || n > MAX_N || !valid_precision(precision))
+        return 0;
+    return make_layout(n, precision).minimum;
+}
+
 extern "C" int hawkes_loglik(const hawkes_events *events, const hawkes_theta *theta, int precision,
                              int64_t row_begin, int64_t row_end, void *ws, size_t ws_bytes, double *d_loglik,
-                             void *stream)
+                             const hawkes_options *opts, void *stream)
 {
-    return run(events, theta, precision, row_begin, row_end, ws, ws_bytes, d_loglik, nullptr, nullptr, nullptr,
-               MODE_LOGLIK, stream);
+    return run(events, theta, precision, row_begin, row_end, ws, ws_bytes, opts, d_loglik, nullptr, nullptr,
+               nullptr, MODE_LOGLIK, stream);
 }
 
 extern "C" int hawkes_loglik_grad(const hawkes_events *events, const hawkes_theta *theta, int precision,
                                   int64_t row_begin, int64_t row_end, void *ws, size_t ws_bytes, double *d_loglik,
-                                  double *d_grad, void *stream)
+                                  double *d_grad, const hawkes_options *opts, void *stream)
 {
-    return run(events, theta, precision, row_begin, row_end, ws, ws_bytes, d_loglik, d_grad, nullptr, nullptr,
-               MODE_GRAD, stream);
+    return run(events, theta, precision, row_begin, row_end, ws, ws_bytes, opts, d_loglik, d_grad, nullptr,
+               nullptr, MODE_GRAD, stream);
 }
 
 extern "C" int hawkes_event_terms(const hawkes_events *events, const hawkes_theta *theta, int precision,
                                   int64_t row_begin, int64_t row_end, void *ws, size_t ws_bytes, double *d_lambda,
-                                  double *d_comp, void *stream)
+                                  double *d_comp, const hawkes_options *opts, void *stream)
 {
-    return run(events, theta, precision, row_begin, row_end, ws, ws_bytes, nullptr, nullptr, d_lambda, d_comp,
-               MODE_TERMS, stream);
+    return run(events, theta, precision, row_begin, row_end, ws, ws_bytes, opts, nullptr, nullptr, d_lambda,
+               d_comp, MODE_TERMS, stream);
 }
 
 extern "C" int hawkes_loglik_batch(const hawkes_events *events, const hawkes_theta *thetas, int64_t num_theta,
                                    int precision, int64_t row_begin, int64_t row_end, void *ws, size_t ws_bytes,
-                                   double *d_loglik, void *stream)
+                                   double *d_loglik, const hawkes_options *opts, void *stream)
 {
-    return run_batch(events, thetas, num_theta, precision, row_begin, row_end, ws, ws_bytes, d_loglik, stream);
+    return run_batch(events, thetas, num_theta, precision, row_begin, row_end, ws, ws_bytes, opts, d_loglik,
+                     stream);
 }
 
 extern "C" int hawkes_workspace_status(const void *ws, int *status, void *stream)
@@ -2633,36 +2978,6 @@ extern "C" int hawkes_workspace_status(const void *ws, int *status, void *stream
     return HAWKES_OK;
 }
 
-extern "C" int hawkes_set_timing(int enable)
-{
-    if (enable && !g_ev_start) {
-        hipError_t e = hipEventCreate(&g_ev_start);
-        if (e == hipSuccess)
-            e = hipEventCreate(&g_ev_stop);
-        if (e != hipSuccess)
-            return hip_failure(e, "hipEventCreate");
-    }
-    g_timing = enable != 0;
-    g_timing_recorded = false;
-    return HAWKES_OK;
-}
-
-extern "C" int hawkes_last_pair_kernel_ms(float *ms)
-{
-    if (!ms) {
-        set_error("null output pointer");
-        return HAWKES_EINVAL;
-    }
-    if (!g_timing_recorded) {
-        set_error("no timed pair kernel since timing was enabled");
-        return HAWKES_EINVAL;
-    }
-    hipError_t e = hipEventSynchronize(g_ev_stop);
-    if (e == hipSuccess)
-        e = hipEventElapsedTime(ms, g_ev_start, g_ev_stop);
-    return e == hipSuccess ? HAWKES_OK : hip_failure(e, "hipEventElapsedTime");
-}
-
 extern "C" const char *hawkes_strerror(int status)
 {
     switch (status) {
@@ -2678,23 +2993,3 @@ extern "C" const char *hawkes_strerror(int status)
 }
 
 extern "C" const char *hawkes_last_error(void) { return g_errbuf; }
-
-// Tuning hook (not part of the public header): workgroups the pair sweep aims
-// for per call; bounded by the workspace sizing.
-extern "C" int hawkes_tune_target_workgroups(int64_t wgs)
-{
-    if (wgs < 1 || wgs > MAX_TARGET_WGS)
-        return HAWKES_EINVAL;
-    g_target_wgs = wgs;
-    return HAWKES_OK;
-}
-
-// Tuning hook (not part of the public header): groups of the symmetric FP32
-// sweep (0 = whole-set calls take the row sweep as well).
-extern "C" int hawkes_tune_symmetric_groups(int64_t groups)
-{
-    if (groups < 0 || groups > MAX_SYM_GROUPS)
-        return HAWKES_EINVAL;
-    g_sym_groups = int(groups);
-    return HAWKES_OK;
-}

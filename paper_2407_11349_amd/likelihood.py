@@ -50,13 +50,21 @@ def workspace_bytes(n: int, precision="fp32") -> int:
     return int(_lib.load().hawkes_workspace_bytes(int(n), _lib.precision_code(precision)))
 
 
+def workspace_min_bytes(n: int, precision="fp32") -> int:
+    return int(_lib.load().hawkes_workspace_min_bytes(int(n), _lib.precision_code(precision)))
+
+
 class Workspace:
     """Caller-owned device scratch for the likelihood calls (allocated once)."""
 
-    def __init__(self, n: int, precision="fp32", device="cuda"):
-        nbytes = workspace_bytes(n, precision)
-        if nbytes == 0:
+    def __init__(self, n: int, precision="fp32", device="cuda", nbytes: int | None = None):
+        """nbytes: the workspace size (default hawkes_workspace_bytes; a larger one gives the sweep's
+        passes more room, a smaller one below the minimum is refused by the calls)."""
+        need = workspace_bytes(n, precision)
+        if need == 0:
             raise ValueError(f"invalid workspace request n={n} precision={precision}")
+        nbytes = need if nbytes is None else int(nbytes)
+        nbytes = (nbytes + 255) // 256 * 256
         self.nbytes = nbytes
         # over-allocate so the base can be aligned to 256 bytes
         self._buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
@@ -74,13 +82,16 @@ class Workspace:
 _WS_CACHE: dict = {}
 
 
-def _workspace(events: DeviceEvents, precision, ws: Workspace | None) -> Workspace:
+def _workspace(events: DeviceEvents, precision, ws: Workspace | None, stream=None) -> Workspace:
+    """The caller's workspace, else one cached per (size, precision, device, stream): calls that share
+    a workspace must not overlap, and calls on one stream never do."""
     if ws is not None:
         return ws
-    key = (events.n, _lib.precision_code(precision), events.t.device)
+    key = (events.n, _lib.precision_code(precision), events.t.device, _lib.stream_handle(stream))
     w = _WS_CACHE.get(key)
     if w is None:
-        _WS_CACHE.clear()
+        if len(_WS_CACHE) >= 4:
+            _WS_CACHE.clear()
         w = Workspace(events.n, precision, events.t.device)
         _WS_CACHE[key] = w
     return w
@@ -93,42 +104,52 @@ def _rows(events: DeviceEvents, rows):
     return int(r0), int(r1)
 
 
-def loglik(events: DeviceEvents, theta, precision="fp32", rows=None, ws=None, out=None, stream=None) -> torch.Tensor:
+# Keyword arguments of every likelihood call, passed to the library as hawkes_options:
+#   symmetric_groups  0 = default (384), 1..1024, or -1 = whole-set calls take the row sweep
+#   row_workgroups    0 = default (32768), else 1..65536
+#   timer             a SweepTimer whose events the call records around its pair sweep
+
+
+def loglik(events: DeviceEvents, theta, precision="fp32", rows=None, ws=None, out=None, stream=None, *,
+           symmetric_groups=0, row_workgroups=0, timer=None) -> torch.Tensor:
     """Log-likelihood of rows [r0, r1) as a 1-element float64 device tensor (asynchronous)."""
     lib = _lib.load()
-    w = _workspace(events, precision, ws)
+    w = _workspace(events, precision, ws, stream)
     r0, r1 = _rows(events, rows)
     out = torch.empty(1, dtype=torch.float64, device=events.t.device) if out is None else out
     ev = events.struct()
     th = _lib.theta_struct(theta)
+    o = _lib.options(row_workgroups, symmetric_groups, timer)
     _lib.check(lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(th), _lib.precision_code(precision), r0, r1,
-                                 w.ptr, w.nbytes, _lib.ptr(out), _lib.stream_handle(stream)), "hawkes_loglik")
+                                 w.ptr, w.nbytes, _lib.ptr(out), _lib.opt_ref(o), _lib.stream_handle(stream)),
+               "hawkes_loglik")
     return out
 
 
 def loglik_grad(events: DeviceEvents, theta, precision="fp32", rows=None, ws=None, out=None, grad=None,
-                stream=None):
+                stream=None, *, symmetric_groups=0, row_workgroups=0, timer=None):
     """(loglik (1,), gradient (6,)) float64 device tensors, gradient w.r.t. natural theta."""
     lib = _lib.load()
-    w = _workspace(events, precision, ws)
+    w = _workspace(events, precision, ws, stream)
     r0, r1 = _rows(events, rows)
     dev = events.t.device
     out = torch.empty(1, dtype=torch.float64, device=dev) if out is None else out
     grad = torch.empty(6, dtype=torch.float64, device=dev) if grad is None else grad
     ev = events.struct()
     th = _lib.theta_struct(theta)
+    o = _lib.options(row_workgroups, symmetric_groups, timer)
     _lib.check(lib.hawkes_loglik_grad(ctypes.byref(ev), ctypes.byref(th), _lib.precision_code(precision), r0, r1,
-                                      w.ptr, w.nbytes, _lib.ptr(out), _lib.ptr(grad), _lib.stream_handle(stream)),
-               "hawkes_loglik_grad")
+                                      w.ptr, w.nbytes, _lib.ptr(out), _lib.ptr(grad), _lib.opt_ref(o),
+                                      _lib.stream_handle(stream)), "hawkes_loglik_grad")
     return out, grad
 
 
 def loglik_batch(events: DeviceEvents, thetas, precision="fp32", rows=None, ws=None, out=None,
-                 stream=None) -> torch.Tensor:
+                 stream=None, *, symmetric_groups=0, row_workgroups=0, timer=None) -> torch.Tensor:
     """Log-likelihoods of rows [r0, r1) at each of K parameter vectors (a (K, 6) array-like) as a
     K-element float64 device tensor (asynchronous); FP32 evaluates them two per pair sweep."""
     lib = _lib.load()
-    w = _workspace(events, precision, ws)
+    w = _workspace(events, precision, ws, stream)
     r0, r1 = _rows(events, rows)
     arr = _lib.theta_array(thetas)
     k = len(arr)
@@ -136,24 +157,28 @@ def loglik_batch(events: DeviceEvents, thetas, precision="fp32", rows=None, ws=N
     if out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous() or out.numel() < k:
         raise ValueError("out must be a contiguous float64 CUDA tensor of at least K elements")
     ev = events.struct()
+    o = _lib.options(row_workgroups, symmetric_groups, timer)
     _lib.check(lib.hawkes_loglik_batch(ctypes.byref(ev), arr, k, _lib.precision_code(precision), r0, r1, w.ptr,
-                                       w.nbytes, _lib.ptr(out), _lib.stream_handle(stream)), "hawkes_loglik_batch")
+                                       w.nbytes, _lib.ptr(out), _lib.opt_ref(o), _lib.stream_handle(stream)),
+               "hawkes_loglik_batch")
     return out
 
 
-def event_terms(events: DeviceEvents, theta, precision="fp32", rows=None, ws=None, stream=None):
+def event_terms(events: DeviceEvents, theta, precision="fp32", rows=None, ws=None, stream=None, *,
+                symmetric_groups=0, row_workgroups=0, timer=None):
     """(lambda_n, Lambda_n) for the rows, float64 device tensors."""
     lib = _lib.load()
-    w = _workspace(events, precision, ws)
+    w = _workspace(events, precision, ws, stream)
     r0, r1 = _rows(events, rows)
     dev = events.t.device
     lam = torch.empty(r1 - r0, dtype=torch.float64, device=dev)
     comp = torch.empty(r1 - r0, dtype=torch.float64, device=dev)
     ev = events.struct()
     th = _lib.theta_struct(theta)
+    o = _lib.options(row_workgroups, symmetric_groups, timer)
     _lib.check(lib.hawkes_event_terms(ctypes.byref(ev), ctypes.byref(th), _lib.precision_code(precision), r0, r1,
-                                      w.ptr, w.nbytes, _lib.ptr(lam), _lib.ptr(comp), _lib.stream_handle(stream)),
-               "hawkes_event_terms")
+                                      w.ptr, w.nbytes, _lib.ptr(lam), _lib.ptr(comp), _lib.opt_ref(o),
+                                      _lib.stream_handle(stream)), "hawkes_event_terms")
     return lam, comp
 
 
@@ -173,14 +198,7 @@ def resample_locations(county: torch.Tensor, rect: torch.Tensor, seed: int, iter
                "hawkes_resample_locations")
 
 
-def set_timing(enable: bool) -> None:
-    _lib.check(_lib.load().hawkes_set_timing(1 if enable else 0), "hawkes_set_timing")
-
-
-def last_pair_kernel_ms() -> float:
-    ms = ctypes.c_float(0.0)
-    _lib.check(_lib.load().hawkes_last_pair_kernel_ms(ctypes.byref(ms)), "hawkes_last_pair_kernel_ms")
-    return float(ms.value)
+SweepTimer = _lib.SweepTimer
 
 
 class HawkesLoglik(torch.autograd.Function):

@@ -228,16 +228,10 @@ def test_chunking_does_not_change_results_beyond_rounding(prec):
     ev = synth.generate(synth.N2K, n=9000, seed=10)
     th = synth.theta_default()
     dev = _dev(ev)
-    lib = _lib.load()
     vals = []
-    try:
-        assert lib.hawkes_tune_symmetric_groups(0) == 0
-        for wgs in (1, 64, 4096, 65536):
-            assert lib.hawkes_tune_target_workgroups(wgs) == 0
-            vals.append(_gpu_ll_grad(dev, th, prec))
-    finally:
-        lib.hawkes_tune_target_workgroups(32768)
-        lib.hawkes_tune_symmetric_groups(_lib.SYM_GROUPS_DEFAULT)
+    for wgs in (1, 64, 4096, 65536):
+        ll, g = hk.loglik_grad(dev, th, precision=prec, symmetric_groups=-1, row_workgroups=wgs)
+        vals.append((float(ll.item()), g.cpu().numpy()))
     for ll, g in vals[1:]:
         assert ll == pytest.approx(vals[0][0], rel=1e-11)
         np.testing.assert_allclose(g, vals[0][1], rtol=1e-8)
@@ -265,16 +259,16 @@ def test_device_data_checks():
         assert ws.status() == _lib.HAWKES_OK and math.isfinite(float(ok.item()))
 
 
-def test_pair_kernel_timing_hook():
+def test_pair_sweep_timing_events():
+    """The caller's events (hawkes_options.timing_start/stop) bracket the pair sweep on the call's
+    stream; two timers on two calls do not interfere."""
     ev = synth.generate(synth.N2K, n=20000, seed=1)
     dev = _dev(ev)
-    hk.set_timing(True)
-    try:
-        hk.loglik_grad(dev, synth.theta_default(), precision="fp32")
-        ms = hk.last_pair_kernel_ms()
-    finally:
-        hk.set_timing(False)
-    assert 0.0 < ms < 1000.0
+    t1, t2 = hk.SweepTimer(), hk.SweepTimer()
+    hk.loglik_grad(dev, synth.theta_default(), precision="fp32", timer=t1)
+    hk.loglik(dev, synth.theta_default(), precision="fp64", timer=t2)
+    ms1, ms2 = t1.elapsed_ms(), t2.elapsed_ms()
+    assert 0.0 < ms1 < 1000.0 and 0.0 < ms2 < 1000.0
 
 
 def test_fp32_rescue_of_underflow_limited_rows():

@@ -1,0 +1,98 @@
+"""GPU checks of the pass structure of the pair sweep: the sweep's workgroups write partial sums
+into a slot region of the workspace and a fold kernel adds each pass's slots into per-row FP64
+accumulators in a fixed cell order, so results must be bitwise the same whatever the workspace
+size (one pass, several, or one workgroup per pass), for the symmetric sweep, the row sweep and
+the two-vector sweep, at FP32 and FP64.  A workspace below the minimum is refused."""
+
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+import paper_2407_11349_amd as hk
+from paper_2407_11349_amd import _lib
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _events(kind, n, seed):
+    ev = synth.generate(synth.N2K, n=n, seed=seed)
+    t = ev.t if kind == "dense" else np.floor(ev.t / 20.0) * 20.0  # five distinct times: long tie runs
+    return hk.DeviceEvents.from_arrays(t, ev.x, ev.y, ev.s)
+
+
+def _all_outputs(dev, th, prec, ws):
+    ll, g = hk.loglik_grad(dev, th, precision=prec, ws=ws)
+    l1 = hk.loglik(dev, th, precision=prec, ws=ws)
+    lam, comp = hk.event_terms(dev, th, precision=prec, ws=ws)
+    lr, gr = hk.loglik_grad(dev, th, precision=prec, ws=ws, rows=(dev.n // 3, dev.n - 5))
+    lrow, grow = hk.loglik_grad(dev, th, precision=prec, ws=ws, symmetric_groups=-1)
+    th2 = np.stack([th, th * np.array([1.03, 0.97, 1.02, 0.98, 1.04, 0.96])])
+    lb = hk.loglik_batch(dev, th2, precision=prec, ws=ws)
+    torch.cuda.synchronize()
+    assert ws.status() == _lib.HAWKES_OK
+    return [x.cpu().numpy() for x in (ll, g, l1, lam, comp, lr, gr, lrow, grow, lb)]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "fp32_skip"])
+@pytest.mark.parametrize("kind", ["dense", "five_days"])
+def test_results_do_not_depend_on_workspace_size(prec, kind):
+    n = 9000
+    dev = _events(kind, n, 31)
+    th = synth.theta_default()
+    full = hk.workspace_bytes(n, prec)
+    lo = hk.workspace_min_bytes(n, prec)
+    # symmetric cell at n = 9000: 9 sums x 512 events x 8 bytes
+    cell = 9 * 512 * 8
+    sizes = [full, full + 64 * cell, lo + 7 * cell, lo + 2 * cell, lo]
+    ref = None
+    for nbytes in sizes:
+        _say(f"passes test: {kind} {prec} workspace {nbytes} bytes")
+        ws = hk.Workspace(n, prec, nbytes=nbytes)
+        out = _all_outputs(dev, th, prec, ws)
+        assert all(np.all(np.isfinite(x)) for x in out)
+        if ref is None:
+            ref = out
+        else:
+            for a, b in zip(ref, out):
+                assert np.array_equal(a, b), (kind, prec, nbytes)
+        del ws
+
+
+def test_workspace_below_minimum_is_refused():
+    n = 5000
+    dev = _events("dense", n, 3)
+    th = synth.theta_default()
+    lo = hk.workspace_min_bytes(n, "fp32")
+    ws = hk.Workspace(n, "fp32", nbytes=lo - 256)
+    with pytest.raises(_lib.HawkesError) as e:
+        hk.loglik_grad(dev, th, precision="fp32", ws=ws)
+    assert e.value.status == -3
+    # fewer symmetric groups make a workgroup's slot larger than the minimum workspace holds
+    ws = hk.Workspace(n, "fp32", nbytes=lo)
+    with pytest.raises(_lib.HawkesError) as e:
+        hk.loglik_grad(dev, th, precision="fp32", ws=ws, symmetric_groups=2)
+    assert e.value.status == -3
+    ll, _ = hk.loglik_grad(dev, th, precision="fp32", ws=ws)
+    assert np.isfinite(float(ll.item()))
+
+
+def test_group_counts_agree():
+    """Symmetric group counts up to the largest accepted (1024 > the 18 blocks here: one block per
+    group) agree to FP64 summation order."""
+    n = 9000
+    dev = _events("dense", n, 5)
+    th = synth.theta_default()
+    vals = []
+    for groups in (1, 3, 7, 384, _lib.SYM_GROUPS_MAX):
+        ll, g = hk.loglik_grad(dev, th, precision="fp32", symmetric_groups=groups)
+        vals.append((float(ll.item()), g.cpu().numpy()))
+    for ll, g in vals[1:]:
+        assert ll == pytest.approx(vals[0][0], rel=1e-12)
+        np.testing.assert_allclose(g, vals[0][1], rtol=1e-9)

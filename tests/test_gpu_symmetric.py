@@ -26,15 +26,12 @@ def _say(msg):
 
 
 def _run(dev, th, prec="fp32", groups=DEFAULT_GROUPS):
-    lib = _lib.load()
-    assert lib.hawkes_tune_symmetric_groups(groups) == 0
-    try:
-        ll, g = hk.loglik_grad(dev, th, precision=prec)
-        lam, comp = hk.event_terms(dev, th, precision=prec)
-        torch.cuda.synchronize()
-        return float(ll.item()), g.cpu().numpy(), lam.cpu().numpy(), comp.cpu().numpy()
-    finally:
-        lib.hawkes_tune_symmetric_groups(DEFAULT_GROUPS)
+    """groups: the symmetric sweep's group count, or 0 for the row sweep over the whole set."""
+    sg = groups if groups > 0 else -1
+    ll, g = hk.loglik_grad(dev, th, precision=prec, symmetric_groups=sg)
+    lam, comp = hk.event_terms(dev, th, precision=prec, symmetric_groups=sg)
+    torch.cuda.synchronize()
+    return float(ll.item()), g.cpu().numpy(), lam.cpu().numpy(), comp.cpu().numpy()
 
 
 def _events(kind, n, seed):

@@ -29,7 +29,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = _declared()
-    assert len(names) >= 18
+    assert len(names) >= 17
     for name in names:
         assert hasattr(lib, name), name
     assert set(names) == set(_lib.EXPORTS)
@@ -47,6 +47,15 @@ def test_workspace_bytes(lib):
         assert a % 256 == 0 and c % 256 == 0
     # FP32 keeps extra staged source records
     assert lib.hawkes_workspace_bytes(5000, 1) > lib.hawkes_workspace_bytes(5000, 0)
+    # O(n): a part linear in n plus a slot region of at most 768 MiB (under 1 GiB at 10^6 events)
+    assert lib.hawkes_workspace_bytes(1_000_000, 1) < 2**30
+    big = lib.hawkes_workspace_bytes(4_000_000, 1) - lib.hawkes_workspace_bytes(2_000_000, 1)
+    assert big < 2_000_000 * 260
+    for prec in (0, 1, 2):
+        for n in (1, 700, 20_000, 1_000_000):
+            lo, hi = lib.hawkes_workspace_min_bytes(n, prec), lib.hawkes_workspace_bytes(n, prec)
+            assert 0 < lo <= hi and lo % 256 == 0
+    assert lib.hawkes_workspace_min_bytes(0, 1) == 0
 
 
 def test_strerror_and_codes(lib):
@@ -64,40 +73,47 @@ def test_host_validation_paths(lib):
     ev = _ev(1000)
     ws_need = lib.hawkes_workspace_bytes(1000, 1)
     fake = 0x200000  # never dereferenced: every call below fails host validation
-    assert lib.hawkes_loglik(None, ctypes.byref(th), 1, 0, 10, fake, ws_need, fake, None) == -1
-    assert lib.hawkes_loglik(ctypes.byref(_ev(0)), ctypes.byref(th), 1, 0, 0, fake, ws_need, fake, None) == -1
-    assert lib.hawkes_loglik(ctypes.byref(_ev(1000, 0)), ctypes.byref(th), 1, 0, 1, fake, ws_need, fake, None) == -1
-    assert lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(th), 3, 0, 10, fake, ws_need, fake, None) == -1
+    assert lib.hawkes_loglik(None, ctypes.byref(th), 1, 0, 10, fake, ws_need, fake, None, None) == -1
+    assert lib.hawkes_loglik(ctypes.byref(_ev(0)), ctypes.byref(th), 1, 0, 0, fake, ws_need, fake, None,
+                             None) == -1
+    assert lib.hawkes_loglik(ctypes.byref(_ev(1000, 0)), ctypes.byref(th), 1, 0, 1, fake, ws_need, fake, None,
+                             None) == -1
+    assert lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(th), 3, 0, 10, fake, ws_need, fake, None, None) == -1
     for bad_area in (-1.0, float("nan"), float("inf")):
         eva = _ev(1000, area=bad_area)
-        assert lib.hawkes_loglik(ctypes.byref(eva), ctypes.byref(th), 1, 0, 10, fake, ws_need, fake, None) == -1
+        assert lib.hawkes_loglik(ctypes.byref(eva), ctypes.byref(th), 1, 0, 10, fake, ws_need, fake, None, None) == -1
         assert b"area" in lib.hawkes_last_error()
     for k in range(6):
         for bad in (0.0, -1.0, float("nan"), float("inf")):
             vals = [0.5, 10.0, 7.0, 0.3, 2.0, 0.2]
             vals[k] = bad
             tb = _lib.Theta(*vals)
-            assert lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(tb), 1, 0, 10, fake, ws_need, fake, None) == -1
+            assert lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(tb), 1, 0, 10, fake, ws_need, fake, None, None) == -1
     assert b"theta" in lib.hawkes_last_error()
     for r0, r1 in ((-1, 5), (0, 1001), (7, 6)):
         assert lib.hawkes_loglik_grad(ctypes.byref(ev), ctypes.byref(th), 1, r0, r1, fake, ws_need, fake, fake,
-                                      None) == -2
-    assert lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(th), 1, 0, 10, fake, ws_need - 256, fake, None) == -3
-    assert lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(th), 1, 0, 10, fake + 8, ws_need, fake, None) == -3
-    assert lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(th), 1, 0, 10, None, ws_need, fake, None) == -3
-    assert lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(th), 1, 0, 10, fake, ws_need, None, None) == -1
+                                      None, None) == -2
+    ws_min = lib.hawkes_workspace_min_bytes(1000, 1)
+    assert lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(th), 1, 0, 10, fake, ws_min - 256, fake, None, None) == -3
+    assert lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(th), 1, 0, 10, fake + 8, ws_need, fake, None, None) == -3
+    assert lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(th), 1, 0, 10, None, ws_need, fake, None, None) == -3
+    assert lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(th), 1, 0, 10, fake, ws_need, None, None, None) == -1
     assert lib.hawkes_loglik_grad(ctypes.byref(ev), ctypes.byref(th), 1, 0, 10, fake, ws_need, fake, None,
-                                  None) == -1
+                                  None, None) == -1
     assert lib.hawkes_resample_locations(10, None, fake, 3, 1, 2, fake, fake, None) == -1
     assert lib.hawkes_resample_locations(10, fake, fake, 0, 1, 2, fake, fake, None) == -1
     assert lib.hawkes_resample_locations(0, None, None, 3, 1, 2, None, None, None) == 0
-    assert lib.hawkes_tune_target_workgroups(0) == -1
-    assert lib.hawkes_tune_target_workgroups(10**6) == -1
-    assert lib.hawkes_tune_symmetric_groups(-1) == -1
-    assert lib.hawkes_tune_symmetric_groups(_lib.SYM_GROUPS_DEFAULT + 1) == -1
-    # the binding's default is the library's largest accepted group count
-    assert lib.hawkes_tune_symmetric_groups(_lib.SYM_GROUPS_DEFAULT) == 0
-    assert lib.hawkes_last_pair_kernel_ms(None) == -1
+    # per-call options out of range are refused before any work is enqueued
+    for kw in ({"row_workgroups": -1}, {"row_workgroups": _lib.ROW_WGS_MAX + 1},
+               {"symmetric_groups": -2}, {"symmetric_groups": _lib.SYM_GROUPS_MAX + 1}, {"reserved": 1},
+               {"timing_start": fake}):
+        o = _lib.Options(**kw)
+        assert lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(th), 1, 0, 10, fake, ws_need, fake,
+                                 ctypes.byref(o), None) == -1
+    # the largest accepted values pass the option checks (and then fail on the workspace)
+    o = _lib.Options(row_workgroups=_lib.ROW_WGS_MAX, symmetric_groups=_lib.SYM_GROUPS_MAX)
+    assert lib.hawkes_loglik(ctypes.byref(ev), ctypes.byref(th), 1, 0, 10, fake, 256, fake, ctypes.byref(o),
+                             None) == -3
 
 
 def test_batch_host_validation(lib):
@@ -107,18 +123,19 @@ def test_batch_host_validation(lib):
     good = (0.5, 10.0, 7.0, 0.3, 2.0, 0.2)
     arr = (_lib.Theta * 3)(_lib.Theta(*good), _lib.Theta(*good), _lib.Theta(*good))
     call = lib.hawkes_loglik_batch
-    assert call(ctypes.byref(ev), arr, 0, 1, 0, 10, fake, ws_need, fake, None) == -1
-    assert call(ctypes.byref(ev), None, 2, 1, 0, 10, fake, ws_need, fake, None) == -1
-    assert call(ctypes.byref(ev), arr, 2, 1, 0, 10, fake, ws_need, None, None) == -1
-    assert call(ctypes.byref(ev), arr, 2, 7, 0, 10, fake, ws_need, fake, None) == -1
-    assert call(ctypes.byref(ev), arr, 2, 1, 0, 1001, fake, ws_need, fake, None) == -2
-    assert call(ctypes.byref(ev), arr, 2, 1, 0, 10, fake, ws_need - 256, fake, None) == -3
+    assert call(ctypes.byref(ev), arr, 0, 1, 0, 10, fake, ws_need, fake, None, None) == -1
+    assert call(ctypes.byref(ev), None, 2, 1, 0, 10, fake, ws_need, fake, None, None) == -1
+    assert call(ctypes.byref(ev), arr, 2, 1, 0, 10, fake, ws_need, None, None, None) == -1
+    assert call(ctypes.byref(ev), arr, 2, 7, 0, 10, fake, ws_need, fake, None, None) == -1
+    assert call(ctypes.byref(ev), arr, 2, 1, 0, 1001, fake, ws_need, fake, None, None) == -2
+    ws_min = lib.hawkes_workspace_min_bytes(1000, 1)
+    assert call(ctypes.byref(ev), arr, 2, 1, 0, 10, fake, ws_min - 256, fake, None, None) == -3
     # a bad component in any vector is caught before work is enqueued
     for k in range(3):
         vals = list(good)
         vals[5] = float("nan")
         bad = (_lib.Theta * 3)(*[_lib.Theta(*(vals if j == k else good)) for j in range(3)])
-        assert call(ctypes.byref(ev), bad, 3, 1, 0, 10, fake, ws_need, fake, None) == -1
+        assert call(ctypes.byref(ev), bad, 3, 1, 0, 10, fake, ws_need, fake, None, None) == -1
         assert b"theta" in lib.hawkes_last_error()
     # theta_array marshals (K, 6) inputs and rejects bad shapes
     a = _lib.theta_array([good, good])
