@@ -96,6 +96,28 @@ def pair_counts(t: np.ndarray) -> tuple[int, int]:
     return bg, causal
 
 
+def parity_vs_stored_oracle(hk, torch, ev, th, ws32) -> dict | None:
+    """Untimed: FP32 and FP64 loglik+grad at the generator's locations against the FP64 oracle's
+    stored value of this workload (tests/golden/oracle_values.json, written from oracle/ only);
+    relative errors, the gradient's per component (max) and as a vector norm."""
+    path = os.path.join(ROOT, "tests", "golden", "oracle_values.json")
+    gold = json.load(open(path)).get("n1m") if os.path.exists(path) else None
+    if gold is None or gold["n"] != ev.n or not np.allclose(gold["theta"], th):
+        return None
+    dev = hk.DeviceEvents.from_arrays(ev.t, ev.x, ev.y, ev.s, device="cuda")
+    g_ref = np.array(gold["grad"])
+    out = {"reference": "FP64 oracle, stored (n1m, generator locations)", "tolerance": {"loglik": 1e-9, "grad": 1e-6}}
+    for prec in ("fp32", "fp64"):
+        ws = ws32 if prec == "fp32" else hk.Workspace(ev.n, "fp64")
+        ll, g = hk.loglik_grad(dev, th, precision=prec, ws=ws)
+        torch.cuda.synchronize()
+        ll, g = float(ll.item()), g.cpu().numpy()
+        out[prec] = {"loglik_rel_err": abs(ll - gold["loglik"]) / abs(gold["loglik"]),
+                     "grad_rel_err_max": float(np.max(np.abs(g - g_ref) / np.abs(g_ref))),
+                     "grad_rel_err_norm": float(np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref))}
+    return out
+
+
 def cpu_baseline(ev, th, budget_s: float = 15.0) -> dict:
     """The FP64 oracle on a bounded sample of target rows x all sources."""
     import oracle
@@ -264,6 +286,35 @@ def run_ess(args, hk, synth, torch):
     print(json.dumps(res), flush=True)
 
 
+def run_campaign(args, hk, synth, torch):
+    """The comparison of plain HMC and surrogate DA-HMC at 1e6 events as a resumable campaign: continues the
+    run checkpointed in args.ess_campaign until the deadline, saves, and prints the summary so far.  Workload:
+    the clustered (branching-process) event set at the shape of the 1e6 benchmark (1200 days, 50 x 60
+    counties, LogNormal(5, 1.5) densities), FP32 skip-mode likelihood, 20 leapfrog steps."""
+    from paper_2407_11349_amd.mcmc.campaign import Campaign, CampaignConfig, GPUHooks
+    from paper_2407_11349_amd.mcmc.cut import HawkesCutTarget
+
+    t_start = time.time()
+    ev = synth.generate_clustered(n=args.ess_n, t_max=1200.0, rho_sdlog=1.5, seed=1104)
+    log(f"campaign workload {ev.config.name}: {ev.n} events generated in {time.time() - t_start:.1f} s")
+    dev = hk.DeviceEvents.from_arrays(ev.t, ev.x, ev.y, ev.s, device="cuda")
+    county = torch.from_numpy(ev.county).cuda()
+    rect = torch.from_numpy(ev.rect).cuda()
+    target = HawkesCutTarget(dev, county, rect, seed=2004, precision="fp32_skip")
+    cfg = CampaignConfig(n_warmup=args.campaign_warmup, n_plain=args.campaign_plain, n_da=args.ess_iter,
+                         n_leapfrog=20)
+    c = Campaign(args.ess_campaign, target, GPUHooks(log=log), cfg, log=log)
+    phase = c.run(deadline_s=args.deadline_s)
+    out = {"metric": "ESS/s surrogate-HMC vs plain HMC", "unit": "ratio", "higher_is_better": True,
+           "data": "synthetic", "phase": phase,
+           "config": {"workload": ev.config.name, "n_events": ev.n, "step": "resample X + sampler iteration",
+                      **cfg.__dict__},
+           "summary": c.summary()}
+    with open(os.path.join(args.ess_campaign, "summary.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps({k: out[k] for k in ("metric", "phase", "config")}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,6 +332,11 @@ def main():
     ap.add_argument("--ess-warmup", type=int, default=300)
     ap.add_argument("--ess-burn", type=int, default=1000)
     ap.add_argument("--ess-iter", type=int, default=2000)
+    ap.add_argument("--ess-campaign", metavar="DIR", default=None,
+                    help="continue the resumable 1e6-event comparison checkpointed in DIR until --deadline-s")
+    ap.add_argument("--deadline-s", type=float, default=800.0)
+    ap.add_argument("--campaign-warmup", type=int, default=150)
+    ap.add_argument("--campaign-plain", type=int, default=600)
     ap.add_argument("--ess-replicate", type=int, default=0,
                     help="repeat the comparison with other random numbers (latent draws, chains, training)")
     ap.add_argument("--components", action="store_true",
@@ -309,6 +365,9 @@ def main():
     import synth
     import paper_2407_11349_amd as hk
 
+    if args.ess_campaign:
+        run_campaign(args, hk, synth, torch)
+        return
     if args.ess:
         run_ess(args, hk, synth, torch)
         return
@@ -462,6 +521,14 @@ def main():
             "note": "pairs whose background term is exactly 0 in FP32 are not swept; not the O(N^2) metric"}
         log(f"fp32_skip evaluation: {dskip * 1e3:.1f} ms (kernel {kms_skip:.1f} ms)")
         del wss
+
+    if n == synth.N1M.n:
+        par = parity_vs_stored_oracle(hk, torch, ev, th, ws)
+        if par is not None:
+            result["parity"] = par
+            log(f"parity vs stored oracle: fp32 loglik {par['fp32']['loglik_rel_err']:.2e} grad "
+                f"{par['fp32']['grad_rel_err_max']:.2e}; fp64 loglik {par['fp64']['loglik_rel_err']:.2e} grad "
+                f"{par['fp64']['grad_rel_err_max']:.2e}")
 
     comp = component_timings(hk, torch, county, rect, dev.x, dev.y)
     result["components"] = comp

@@ -124,8 +124,7 @@ def test_row_ranges_add_up(prec):
 
 
 def _golden(name):
-    if not os.path.exists(GOLDEN):
-        return None
+    assert os.path.exists(GOLDEN), "tests/golden/oracle_values.json is missing"
     return json.load(open(GOLDEN)).get(name)
 
 
@@ -158,26 +157,31 @@ def test_n100k_sampled_rows_precision_audit():
     _say(f"n100k fp32 per-event lambda: mean rel {rel.mean():.3e} rms {np.sqrt((rel**2).mean()):.3e} "
          f"max {np.abs(rel).max():.3e}")
     assert np.abs(rel).max() <= TOL["fp32"][2]
+    # the mean bias enters the log-likelihood undivided by sqrt(N): at |l|/N ~ 6-8 the 1e-9 target
+    # needs |bias| below ~6e-9 at any N; 2000 rows measure it to ~4e-10 (rms / sqrt(2000))
+    assert abs(rel.mean()) <= 2e-9
 
 
-def test_n1m_sampled_rows_and_stored_oracle():
-    """1e6 events, 1200 days: per-event rates of sampled rows against the oracle,
-    a finite log-likelihood, and (when stored) the full value against the oracle."""
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_n1m_sampled_rows_and_stored_oracle(prec):
+    """1e6 events, 1200 days, in the workspace and pass plan of the benchmark: the full
+    log-likelihood and gradient against the stored oracle value, and per-event rates of sampled
+    rows against the oracle."""
+    gold = _golden("n1m")
+    assert gold is not None, "tests/golden/oracle_values.json lacks n1m"
     ev = synth.generate(synth.N1M)
-    th = synth.theta_default()
+    assert ev.n == gold["n"]
+    th = np.array(gold["theta"])
     dev = _dev(ev)
-    ll, g = _gpu_ll_grad(dev, th, "fp32")
-    assert math.isfinite(ll) and np.isfinite(g).all()
+    ll, g = _gpu_ll_grad(dev, th, prec)
+    _check(ll, g, gold["loglik"], np.array(gold["grad"]), prec, "n1m")
     rng = np.random.default_rng(4)
     rows = np.sort(rng.choice(ev.n - 4, 64, replace=False))
     for a in rows:
         a = int(a)
         lam_ref = oracle.loglik(ev.t, ev.x, ev.y, ev.s, th, rows=(a, a + 4), per_row=True)[2]
-        lam, _ = hk.event_terms(dev, th, precision="fp32", rows=(a, a + 4))
-        np.testing.assert_allclose(lam.cpu().numpy(), lam_ref, rtol=TOL["fp32"][2])
-    gold = _golden("n1m")
-    if gold is not None:
-        _check(ll, g, gold["loglik"], np.array(gold["grad"]), "fp32", "n1m")
+        lam, _ = hk.event_terms(dev, th, precision=prec, rows=(a, a + 4))
+        np.testing.assert_allclose(lam.cpu().numpy(), lam_ref, rtol=TOL[prec][2])
 
 
 def test_resample_bitwise_equals_oracle():
