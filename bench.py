@@ -300,7 +300,8 @@ def run_campaign(args, hk, synth, torch):
     dev = hk.DeviceEvents.from_arrays(ev.t, ev.x, ev.y, ev.s, device="cuda")
     county = torch.from_numpy(ev.county).cuda()
     rect = torch.from_numpy(ev.rect).cuda()
-    target = HawkesCutTarget(dev, county, rect, seed=2004, precision="fp32_skip")
+    target = HawkesCutTarget(dev, county, rect, seed=2004, precision="fp32_skip",
+                             workspace_bytes=(args.workspace_mib << 20) if args.workspace_mib else None)
     cfg = CampaignConfig(n_warmup=args.campaign_warmup, n_plain=args.campaign_plain, n_da=args.ess_iter,
                          n_leapfrog=20)
     c = Campaign(args.ess_campaign, target, GPUHooks(log=log), cfg, log=log)
@@ -321,8 +322,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=None, help="override the event count (testing only)")
-    ap.add_argument("--workspace-mib", type=int, default=0,
-                    help="FP32 workspace size (default: hawkes_workspace_bytes); more room means fewer passes")
+    ap.add_argument("--workspace-mib", type=int, default=4096,
+                    help="FP32 workspace of the timed sweep in MiB (0: hawkes_workspace_bytes); more room means "
+                         "fewer passes of the pair sweep, the same results")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-skip", action="store_true", help="do not time the FP32 skip mode")
@@ -436,6 +438,7 @@ def main():
                    "rho_sdlog": cfg.rho_sdlog, "step": "resample X + FP32 loglik+grad (FP64 finalize)",
                    "parallelism": "single GPU"},
         "loglik_grad_evals_per_s": 1e3 / ms_step,
+        "workspace_bytes": ws.nbytes,
         "roofline": {"bound": "alu", "kernel": "k_pair_f32<grad>", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": measured_traffic(), "kernel_ms": kms, "kernel_source_hash": kernel_source_hash(), "flop_per_launch": flop_per_launch,
@@ -452,6 +455,18 @@ def main():
                                           "fixed per-ordered-pair count; issue bound from the SQ "
                                           "instruction counters of this kernel source"}},
     }
+
+    # the same evaluation in the library's default workspace (hawkes_workspace_bytes: under 1 GiB at 1e6
+    # events, so more passes of the pair sweep)
+    wsd = hk.Workspace(n, "fp32")
+    hk.loglik_grad(dev, th, precision="fp32", ws=wsd, out=out_ll, grad=out_g)
+    tm = hk.SweepTimer()
+    hk.loglik_grad(dev, th, precision="fp32", ws=wsd, out=out_ll, grad=out_g, timer=tm)
+    result["default_workspace"] = {"workspace_bytes": wsd.nbytes, "pair_sweep_ms": tm.elapsed_ms(),
+                                   "note": "pair sweep time with the default workspace (the timed steps use "
+                                           "workspace_bytes above); results are bitwise the same"}
+    log(f"default workspace ({wsd.nbytes / 2**20:.0f} MiB): pair sweep {tm.elapsed_ms():.1f} ms")
+    del wsd
 
     if not args.no_fp64:
         ws64 = hk.Workspace(n, "fp64")
@@ -499,7 +514,7 @@ def main():
     if not args.no_skip:
         # the FP32 sweep without the background terms that are exactly zero in FP32 (time gap
         # past ~14.9 tau_t): same result, less work; reported apart from the O(N^2) metric
-        wss = hk.Workspace(n, "fp32_skip")
+        wss = hk.Workspace(n, "fp32_skip", nbytes=ws.nbytes)
         ll_s = torch.empty(1, dtype=torch.float64, device="cuda")
         g_s = torch.empty(6, dtype=torch.float64, device="cuda")
         hk.loglik_grad(dev, th, precision="fp32_skip", ws=wss, out=ll_s, grad=g_s)

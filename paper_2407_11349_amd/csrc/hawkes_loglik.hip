@@ -297,12 +297,16 @@ struct CellMap {
     const int *total = nullptr;  // symmetric sweep: the plan's cell count
     int num_gr = 0, num_gc = 0;
     int cell0 = 0;               // first cell of the pass being launched
+    int ncells = 0;              // cells of that pass (its workgroups)
 };
 
-// Cell of workgroup w of the current pass (false: past the last cell).
-__host__ __device__ inline bool map_cell(const CellMap &m, unsigned w, int &gr, int &gc)
+// Cell of workgroup w of the current pass and its slot (false: past the last cell).  A pass's
+// workgroups take its cells in reverse order: within a row group the cells nearest the diagonal,
+// the costliest when far pairs are skipped, start first, and the pass ends on cheaper ones.
+__host__ __device__ inline bool map_cell(const CellMap &m, unsigned w, int &gr, int &gc, int &slot)
 {
-    const int c = m.cell0 + int(w);
+    slot = m.ncells - 1 - int(w);
+    const int c = m.cell0 + slot;
     if (!m.rowstart) {
         if (c >= m.num_gr * m.num_gc)
             return false;
@@ -662,8 +666,8 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
 
     constexpr int UJ = GRAD ? HAWKES_UJ_GRAD : HAWKES_UJ;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15;
-    int gr, gc;
-    if (!map_cell(a.cells, blockIdx.x, gr, gc))
+    int gr, gc, slot;
+    if (!map_cell(a.cells, blockIdx.x, gr, gc, slot))
         return;
     const int b_first = gr * a.rr;
     const int b_stop = (b_first + a.rr < a.num_tb) ? b_first + a.rr : a.num_tb;
@@ -672,7 +676,7 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
     // this workgroup's slot: row sums of rows b_first * TB.., column sums of sources kg0 * TS..
     const int64_t stride = a.ge;
     const int jb = kg0 * TS, rb0 = b_first * TB;
-    double *pc = a.scol + int64_t(blockIdx.x) * 3 * stride;
+    double *pc = a.scol + int64_t(slot) * 3 * stride;
     if (a.sym) {
         for (int k = kg0; k < kg1; ++k) {
             const int j = k * TS + tid - jb;
@@ -1080,7 +1084,7 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32(PairF32 a)
         }
 
         // this block's row sums against the column group, in the sums' natural units
-        double *out = a.srow + int64_t(blockIdx.x) * 6 * stride;
+        double *out = a.srow + int64_t(slot) * 6 * stride;
 #pragma unroll
         for (int q = 0; q < KT; ++q) {
             const int i = i0 + tid + q * WG;
@@ -1153,8 +1157,8 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32_batch(PairBatchF32
     __shared__ float lcol[2][NT][NW][TS];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15;
-    int gr, gc;
-    if (!map_cell(a.cells, blockIdx.x, gr, gc))
+    int gr, gc, slot;
+    if (!map_cell(a.cells, blockIdx.x, gr, gc, slot))
         return;
     const int b_first = gr * a.rr;
     const int b_stop = (b_first + a.rr < a.num_tb) ? b_first + a.rr : a.num_tb;
@@ -1162,7 +1166,7 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32_batch(PairBatchF32
     const int kg1 = (kg0 + a.ct < a.num_tiles) ? kg0 + a.ct : a.num_tiles;
     const int64_t stride = a.ge;
     const int jb = kg0 * TS, rb0 = b_first * TB;
-    double *pc = a.scol + int64_t(blockIdx.x) * 3 * stride;
+    double *pc = a.scol + int64_t(slot) * 3 * stride;
     if (a.sym) {
         for (int k = kg0; k < kg1; ++k)
 #pragma unroll
@@ -1505,7 +1509,7 @@ __global__ __launch_bounds__(WG) HK_PAIR_ATTR void k_pair_f32_batch(PairBatchF32
             }
         }
 
-        double *out = a.srow + int64_t(blockIdx.x) * 6 * stride;
+        double *out = a.srow + int64_t(slot) * 6 * stride;
 #pragma unroll
         for (int q = 0; q < KT; ++q) {
             const int i = i0 + tid + q * WG;
@@ -1787,8 +1791,8 @@ __global__ __launch_bounds__(WG) void k_pair_f64(PairF64 a)
     __shared__ double lcol[3][NW][TS];  // per-wave column sums of the tile just swept
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15;
-    int gr, gc;
-    if (!map_cell(a.cells, blockIdx.x, gr, gc))
+    int gr, gc, slot;
+    if (!map_cell(a.cells, blockIdx.x, gr, gc, slot))
         return;
     const int b_first = gr * a.rr;
     const int b_stop = (b_first + a.rr < a.num_tb) ? b_first + a.rr : a.num_tb;
@@ -1796,7 +1800,7 @@ __global__ __launch_bounds__(WG) void k_pair_f64(PairF64 a)
     const int kg1 = (kg0 + a.ct < a.num_tiles) ? kg0 + a.ct : a.num_tiles;
     const int64_t stride = a.ge;
     const int jb = kg0 * TS, rb0 = b_first * TB;
-    double *pc = a.scol + int64_t(blockIdx.x) * 3 * stride;
+    double *pc = a.scol + int64_t(slot) * 3 * stride;
     if (a.sym) {
         for (int k = kg0; k < kg1; ++k) {
             const int j = k * TS + tid - jb;
@@ -1987,7 +1991,7 @@ __global__ __launch_bounds__(WG) void k_pair_f64(PairF64 a)
             }
         }
 
-        double *out = a.srow + int64_t(blockIdx.x) * 6 * stride;
+        double *out = a.srow + int64_t(slot) * 6 * stride;
 #pragma unroll
         for (int q = 0; q < KT; ++q) {
             const int i = i0 + tid + q * WG;
@@ -2482,6 +2486,7 @@ int sweep_passes(const Setup &S, const Tuning &T, int rowmask, int colmask, hipS
         if ((rc = check_launch("pair sweep")) != HAWKES_OK)
             return rc;
         fa.m.cell0 = int(cell0);
+        fa.m.ncells = int(grid);
         fa.ncells = int(grid);
         hipLaunchKernelGGL(k_fold, dim3(unsigned(ceil_div(S.rows, 256))), dim3(256), 0, stream, fa);
         if ((rc = check_launch("fold")) != HAWKES_OK)
@@ -2700,6 +2705,7 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
         }
         rc = sweep_passes(S, T, rowmask, colmask, stream, [&](int cell0, unsigned grid) {
             a.cells.cell0 = cell0;
+            a.cells.ncells = int(grid);
             if (grad && uniform)
                 hipLaunchKernelGGL((k_pair_f32<true, true>), dim3(grid), dim3(WG), 0, stream, a);
             else if (grad)
@@ -2744,6 +2750,7 @@ int run(const hawkes_events *ev, const hawkes_theta *th, int precision, int64_t 
         a.omega = omega * LOG2E;
         rc = sweep_passes(S, T, rowmask, colmask, stream, [&](int cell0, unsigned grid) {
             a.cells.cell0 = cell0;
+            a.cells.ncells = int(grid);
             if (grad)
                 hipLaunchKernelGGL(k_pair_f64<true>, dim3(grid), dim3(WG), 0, stream, a);
             else
@@ -2858,6 +2865,7 @@ int run_batch(const hawkes_events *ev, const hawkes_theta *th, int64_t num_theta
         // vector z's S0 and G0 go to row sums z and 3 + z, its column sums to z
         rc = sweep_passes(S, T, 0x1B, 0x3, stream, [&](int cell0, unsigned grid) {
             a.cells.cell0 = cell0;
+            a.cells.ncells = int(grid);
             if (S.uniform)
                 hipLaunchKernelGGL((k_pair_f32_batch<MAX_FUSED_THETA, true>), dim3(grid), dim3(WG), 0, stream, a);
             else

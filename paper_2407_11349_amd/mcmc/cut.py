@@ -18,14 +18,16 @@ class HawkesCutTarget:
     """log p(z | X, t) = l(exp z; X) + sum_i log N(z_i; 0, prior_sd^2) (up to a constant)."""
 
     def __init__(self, events: lk.DeviceEvents, county: torch.Tensor | None = None, rect: torch.Tensor | None = None,
-                 seed: int = 0, precision: str = "fp32", prior_sd: float = 10.0):
+                 seed: int = 0, precision: str = "fp32", prior_sd: float = 10.0, workspace_bytes: int | None = None):
+        """workspace_bytes: the likelihood workspace (default: hawkes_workspace_bytes); a larger one lets the
+        pair sweep run in fewer passes, with the same results."""
         self.ev = events
         self.county = county
         self.rect = rect
         self.seed = seed
         self.precision = precision
         self.prior_var = prior_sd ** 2
-        self.ws = lk.Workspace(events.n, precision, events.t.device)
+        self.ws = lk.Workspace(events.n, precision, events.t.device, nbytes=workspace_bytes)
         self.out = torch.empty(1, dtype=torch.float64, device=events.t.device)
         self.grad = torch.empty(6, dtype=torch.float64, device=events.t.device)
         self.out_batch = None
