@@ -216,6 +216,22 @@ int hawkes_resample_locations(int64_t n, const int32_t *d_county, const double *
  * HAWKES_EORDER or HAWKES_EDATA. */
 int hawkes_workspace_status(const void *ws, int *status, void *stream);
 
+/* hawkes_loglik_grad without a caller workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the workspace is a 64 MiB array in the
+ * library's own device memory, one copy per GPU the library runs on, held
+ * until the process ends.  Arguments and results as in hawkes_loglik_grad
+ * (bitwise the same values: only the number of sweep passes differs).  n is
+ * limited by the array: calls whose hawkes_workspace_min_bytes(n, precision)
+ * exceeds 64 MiB (about 3 * 10^5 events at FP32) return HAWKES_EWORKSPACE
+ * before any work.  The call allocates nothing.  All calls on one GPU share
+ * the array, so calls that overlap on one GPU (two streams, two threads)
+ * race and must be serialised by the caller; the device status word of the
+ * last call is not readable (data-check failures still give NaN outputs). */
+int hawkes_loglik_grad_noalloc(const hawkes_events *events, const hawkes_theta *theta, int precision,
+                               int64_t row_begin, int64_t row_end, double *d_loglik, double *d_grad,
+                               const hawkes_options *opts, void *stream);
+
 /* Message for a status code, and the calling thread's last error message. */
 const char *hawkes_strerror(int status);
 const char *hawkes_last_error(void);

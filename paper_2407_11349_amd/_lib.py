@@ -28,7 +28,7 @@ HAWKES_EDATA = -6
 # every entry point declared in include/hawkes.h
 EXPORTS = (
     "hawkes_workspace_bytes", "hawkes_workspace_min_bytes", "hawkes_loglik", "hawkes_loglik_grad", "hawkes_event_terms",
-    "hawkes_loglik_batch", "hawkes_resample_locations", "hawkes_workspace_status",
+    "hawkes_loglik_batch", "hawkes_resample_locations", "hawkes_workspace_status", "hawkes_loglik_grad_noalloc",
     "hawkes_strerror", "hawkes_last_error",
     # include/hawkes_mlp.h
     "hawkes_mlp_state_bytes", "hawkes_mlp_workspace_bytes", "hawkes_mlp_load", "hawkes_mlp_store",
@@ -88,6 +88,7 @@ def load(path: Path | str | None = None) -> ctypes.CDLL:
     lib.hawkes_loglik.argtypes = common + [vp, opt_p, vp]
     lib.hawkes_loglik_grad.argtypes = common + [vp, vp, opt_p, vp]
     lib.hawkes_event_terms.argtypes = common + [vp, vp, opt_p, vp]
+    lib.hawkes_loglik_grad_noalloc.argtypes = [ev_p, th_p, ctypes.c_int, i64, i64, vp, vp, opt_p, vp]
     lib.hawkes_loglik_batch.argtypes = [ev_p, th_p, i64, ctypes.c_int, i64, i64, vp, ctypes.c_size_t, vp, opt_p,
                                         vp]
     lib.hawkes_resample_locations.argtypes = [i64, vp, vp, i32, u64, u64, vp, vp, vp]
@@ -108,6 +109,7 @@ def load(path: Path | str | None = None) -> ctypes.CDLL:
     lib.hawkes_last_error.argtypes = []
     lib.hawkes_last_error.restype = ctypes.c_char_p
     for name in ("hawkes_loglik", "hawkes_loglik_grad", "hawkes_event_terms", "hawkes_loglik_batch",
+                 "hawkes_loglik_grad_noalloc",
                  "hawkes_resample_locations",
                  "hawkes_workspace_status", "hawkes_mlp_load",
                  "hawkes_mlp_store", "hawkes_mlp_forward", "hawkes_mlp_leapfrog", "hawkes_mlp_loss_grad",

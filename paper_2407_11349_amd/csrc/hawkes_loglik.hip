@@ -68,6 +68,7 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 
 #include "hawkes.h"
 #include "hawkes_common.h"
@@ -2928,6 +2929,79 @@ extern "C" size_t hawkes_workspace_bytes(int64_t n, int precision)
     if (n < 1 || n > MAX_N || !valid_precision(precision))
         return 0;
     return make_layout(n, precision).total;
+}
+
+// ------------------------------------------------ the entry point that allocates nothing
+//
+// hawkes_loglik_grad_noalloc takes its workspace from a file-scope device
+// array: every GPU the library runs on holds one copy of it at its own
+// address until the process ends.  Host code never names the array as a
+// pointer (that would be a host-side stand-in, not a device address): the
+// device address is looked up once per device with hipGetSymbolAddress and
+// kept.  Calls on one GPU share the array, so calls that overlap on one GPU
+// race; every call clears what must start at zero (status word,
+// accumulators) and stages the rest afresh.
+
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// The current device's address of `scratch` (looked up on the first call on that device).
+int scratch_address(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_failure(e, "hipGetDevice");
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+        set_error("device %d beyond the %d devices hawkes_loglik_grad_noalloc supports", dev, NOALLOC_MAX_DEVICES);
+        return HAWKES_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return hip_failure(e, "hipGetSymbolAddress(scratch)");
+        if (!p || (reinterpret_cast<uintptr_t>(p) & 255u) != 0) {
+            set_error("scratch array of device %d at %p is not 256-byte aligned", dev, p);
+            return HAWKES_EHIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return HAWKES_OK;
+}
+
+}  // namespace
+
+extern "C" int hawkes_loglik_grad_noalloc(const hawkes_events *events, const hawkes_theta *theta, int precision,
+                                          int64_t row_begin, int64_t row_end, double *d_loglik, double *d_grad,
+                                          const hawkes_options *opts, void *stream)
+{
+    // host-side checks first (with a placeholder workspace address), so that invalid calls touch no device
+    Layout L;
+    int rc = validate(events, theta, precision, row_begin, row_end, reinterpret_cast<void *>(uintptr_t(256)),
+                      SIZE_MAX, &L);
+    if (rc != HAWKES_OK)
+        return rc;
+    if (L.minimum > NOALLOC_SCRATCH_BYTES) {
+        set_error("n = %lld needs a workspace of at least %zu bytes at this precision; the static scratch of "
+                  "hawkes_loglik_grad_noalloc holds %zu bytes",
+                  (long long)events->n, L.minimum, NOALLOC_SCRATCH_BYTES);
+        return HAWKES_EWORKSPACE;
+    }
+    void *ws = nullptr;
+    if ((rc = scratch_address(&ws)) != HAWKES_OK)
+        return rc;
+    return run(events, theta, precision, row_begin, row_end, ws, NOALLOC_SCRATCH_BYTES, opts, d_loglik, d_grad,
+               nullptr, nullptr, MODE_GRAD, stream);
 }
 
 extern "C" size_t hawkes_workspace_min_bytes(int64_t n, int precision)

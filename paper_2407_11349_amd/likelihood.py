@@ -144,6 +144,24 @@ def loglik_grad(events: DeviceEvents, theta, precision="fp32", rows=None, ws=Non
     return out, grad
 
 
+def loglik_grad_noalloc(events: DeviceEvents, theta, precision="fp32", rows=None, out=None, grad=None, stream=None,
+                        *, symmetric_groups=0, row_workgroups=0, timer=None):
+    """loglik_grad with the library's own static workspace (hawkes_loglik_grad_noalloc): no device memory
+    is allocated for the call when out and grad are given.  Calls on one GPU must not overlap."""
+    lib = _lib.load()
+    r0, r1 = _rows(events, rows)
+    dev = events.t.device
+    out = torch.empty(1, dtype=torch.float64, device=dev) if out is None else out
+    grad = torch.empty(6, dtype=torch.float64, device=dev) if grad is None else grad
+    ev = events.struct()
+    th = _lib.theta_struct(theta)
+    o = _lib.options(row_workgroups, symmetric_groups, timer)
+    _lib.check(lib.hawkes_loglik_grad_noalloc(ctypes.byref(ev), ctypes.byref(th), _lib.precision_code(precision), r0,
+                                              r1, _lib.ptr(out), _lib.ptr(grad), _lib.opt_ref(o),
+                                              _lib.stream_handle(stream)), "hawkes_loglik_grad_noalloc")
+    return out, grad
+
+
 def loglik_batch(events: DeviceEvents, thetas, precision="fp32", rows=None, ws=None, out=None,
                  stream=None, *, symmetric_groups=0, row_workgroups=0, timer=None) -> torch.Tensor:
     """Log-likelihoods of rows [r0, r1) at each of K parameter vectors (a (K, 6) array-like) as a
