@@ -15,6 +15,8 @@
  * (256 x 256), b3, w4 (256), b4 (1).  The library keeps them in a state
  * buffer (FP32 master weights, Adam moments, BF16 working copies); every
  * forward and backward product uses the BF16 weights with FP32 accumulation.
+ * Batched products run on the matrix cores with each FP32 activation entering
+ * as a hi + lo pair of BF16 values (relative error ~2^-17 per activation).
  *
  * Training minimises the value + gradient ("Sobolev") loss over a batch of B
  * tuples (z_b, y_b, g_b):
@@ -52,7 +54,10 @@ int hawkes_mlp_load(void *d_state, const float *d_params, void *stream);
 int hawkes_mlp_store(const void *d_state, float *d_params, void *stream);
 
 /* Value and input gradient for `batch` inputs: d_z[batch][6] ->
- * d_f[batch], d_gz[batch][6] (d_gz may be NULL). */
+ * d_f[batch], d_gz[batch][6] (d_gz may be NULL).  Batches of up to 8 inputs
+ * take the one-sample kernel, whose arithmetic is that of
+ * hawkes_mlp_leapfrog; larger batches take the matrix cores, 16 inputs per
+ * wave.  The two agree to ~1e-5 relative, not bitwise. */
 int hawkes_mlp_forward(const void *d_state, const float *d_z, int64_t batch, float *d_f, float *d_gz,
                        void *stream);
 
@@ -90,7 +95,9 @@ int hawkes_mlp_leapfrog(const void *d_state, hawkes_mlp_leapfrog_io *d_io, int64
 /* Sobolev loss of a batch (d_z[batch][6], d_y[batch], d_g[batch][6]) into
  * d_loss[1], and its gradient with respect to the flat parameter vector into
  * d_grad[HAWKES_MLP_PARAMS] (if d_grad is NULL, into the workspace).  The
- * gradient is deterministic: per-sample terms are summed in index order. */
+ * gradient is deterministic (every call sums in the same fixed order: matrix
+ * core tiles over 32-sample chunks for W2 and W3, per-lane sums then a fixed
+ * wave butterfly for the other parameters). */
 int hawkes_mlp_loss_grad(const void *d_state, const float *d_z, const float *d_y, const float *d_g,
                          int64_t batch, float lambda_g, void *ws, size_t ws_bytes, float *d_loss,
                          float *d_grad, void *stream);

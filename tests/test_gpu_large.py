@@ -1,6 +1,6 @@
-"""GPU checks at 4e6 events (the 1200-day workload four times as dense; 107 GB of FP32 workspace): sizes
-where offsets into the partial-sum region pass 2^31 elements' worth of bytes and the symmetric sweep runs
-about 70,000 workgroups (373 x 373 groups of 21 blocks).  The full FP64 oracle value is out of reach here (~14 h of CPU), so the checks are
+"""GPU checks at 4e6 events (the 1200-day workload four times as dense), where the symmetric sweep runs about
+70,000 cells (373 x 373 groups of 21 blocks) in passes through the default 1.6 GB FP32 workspace and the
+per-row accumulators hold 4e6 x 9 sums.  The full FP64 oracle value is out of reach here (~14 h of CPU), so the checks are
 per-event rates of sampled rows against the oracle, additivity over row ranges (row sweep against the
 symmetric sweep), the skip mode against the full sweep, and bitwise reproducibility."""
 

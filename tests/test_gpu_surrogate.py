@@ -1,8 +1,9 @@
 """GPU parity of the surrogate-network kernels (through the C ABI) against the FP64
 reference oracle/mlp.py evaluated with the same BF16-rounded weights.
 
-Tolerances: the kernels accumulate 256-term products in FP32 with FP32 GELU, so
-values agree to ~1e-5 of their scale; parameter gradients to ~1e-4 of the
+Tolerances: the kernels accumulate 256-term products in FP32 with FP32 GELU (the
+matrix-core kernels take each FP32 activation as hi + lo BF16 parts, ~2^-17
+relative), so values agree to ~1e-5 of their scale; parameter gradients to ~1e-4 of the
 largest component of their block; Adam updates to FP32 rounding."""
 
 import numpy as np
@@ -26,8 +27,10 @@ def _bf16_params(p32):
     return mlp.to_bf16(p32)
 
 
-@pytest.mark.parametrize("B", [1, 37, 300])
+@pytest.mark.parametrize("B", [1, 8, 9, 16, 37, 300, 4099])
 def test_forward_value_and_input_gradient(B):
+    """Batches of up to 8 take the one-sample kernel, larger ones the matrix-core tiles of 16 samples
+    (ragged last tile at 9, 37, 300 and 4099)."""
     p = init_params(11) * 2.0
     net = SurrogateNet(p)
     z, _, _ = _data(B, 1)
@@ -38,10 +41,12 @@ def test_forward_value_and_input_gradient(B):
     np.testing.assert_allclose(gz.cpu().numpy(), gz_ref, rtol=1e-4, atol=2e-5 * np.abs(gz_ref).max())
 
 
-def test_sobolev_loss_and_parameter_gradient():
+@pytest.mark.parametrize("B", [1, 37, 64, 300])
+def test_sobolev_loss_and_parameter_gradient(B):
+    """Matrix-core training pass over ragged and whole 32-sample chunks of the batch."""
     p = init_params(12) * 2.0
     net = SurrogateNet(p)
-    z, y, g = _data(64, 2)
+    z, y, g = _data(B, 2)
     lam = 0.5
     loss, grad = net.loss_grad(torch.from_numpy(z), torch.from_numpy(y), torch.from_numpy(g), lam)
     torch.cuda.synchronize()
