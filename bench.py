@@ -71,9 +71,10 @@ def profile_fields(name: str) -> dict:
 
 
 def measured_traffic() -> float | None:
-    """HBM bytes per pair-sweep launch from the committed counter summary (None if stale)."""
+    """HBM bytes of one evaluation's pair sweep (its pair-kernel passes and folds) from the committed counter
+    summary (None if stale)."""
     try:
-        return float(profile_fields("pair_f32_n1m_traffic.md")["HBM bytes per launch"])
+        return float(profile_fields("pair_f32_n1m_traffic.md")["HBM bytes per evaluation"])
     except (KeyError, ValueError):
         return None
 
