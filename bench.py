@@ -268,6 +268,28 @@ def sampler_costs(args, hk, synth, torch):
     print(json.dumps(res), flush=True)
 
 
+def run_surrogate_fit(args, hk, synth, torch):
+    """Surrogate training on the 1e5-event workload of the FP32 precision check (1000 days, 3000 counties):
+    exact-HMC burn-in on the cut posterior recording about 20,000 (log theta, l, dl/dlog theta) tuples, 60 epochs
+    of the HIP Sobolev training, and the held-out errors over whole held-out latent-location draws."""
+    from paper_2407_11349_amd.mcmc.experiment import surrogate_fit
+
+    cfg = synth.N100K
+    ev = synth.generate(cfg)
+    dev = hk.DeviceEvents.from_arrays(ev.t, ev.x, ev.y, ev.s, device="cuda")
+    county = torch.from_numpy(ev.county).cuda()
+    rect = torch.from_numpy(ev.rect).cuda()
+    out = surrogate_fit(dev, county, rect, n_burn=args.fit_burn, log=log)
+    held = out["surrogate"]
+    res = {"metric": "surrogate held-out loglik error", "value": held["loglik_rmse_within_draw"], "unit": "nats",
+           "higher_is_better": False, "data": "synthetic",
+           "config": {"workload": cfg.name, "n_events": ev.n, "tuples": held["tuples"], "epochs": held["epochs"],
+                      "network": "6-256-256-256-1 GELU, BF16 weights, FP32 accumulation",
+                      "loss": "Sobolev (value + gradient), lambda 1"},
+           "detail": out}
+    print(json.dumps(res), flush=True)
+
+
 def run_ess(args, hk, synth, torch):
     """ESS/s of delayed-acceptance HMC with the BF16 surrogate against plain exact-gradient HMC, both on the
     cut posterior (X redrawn every iteration) with the FP32 GPU likelihood, 20 leapfrog steps."""
@@ -348,6 +370,10 @@ def main():
                     help="repeat the comparison with other random numbers (latent draws, chains, training)")
     ap.add_argument("--components", action="store_true",
                     help="only time the smaller steps (latent-location draw, surrogate inference and training)")
+    ap.add_argument("--surrogate-fit", action="store_true",
+                    help="train the surrogate on ~20,000 burn-in tuples of the 1e5-event workload and report its "
+                         "held-out error (a few GPU minutes)")
+    ap.add_argument("--fit-burn", type=int, default=952, help="burn-in iterations recorded for --surrogate-fit")
     ap.add_argument("--sampler-costs", type=int, default=0, metavar="N",
                     help="only time the samplers' exact steps on the clustered workload with N events")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -377,6 +403,9 @@ def main():
         return
     if args.ess:
         run_ess(args, hk, synth, torch)
+        return
+    if args.surrogate_fit:
+        run_surrogate_fit(args, hk, synth, torch)
         return
     if args.sampler_costs:
         sampler_costs(args, hk, synth, torch)

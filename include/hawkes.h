@@ -140,8 +140,8 @@ typedef struct hawkes_options {
  * workgroups.  The sweep runs in passes over as many workgroups as the slot
  * region holds, each pass followed by a fold of its partial sums into the
  * per-row accumulators; the returned size gives the slot region the smaller
- * of 768 MiB and what a single pass needs (at least one workgroup's slot):
- * about 0.97 GiB in all at n = 10^6 (FP32).  A larger workspace means fewer
+ * of 704 MiB and what a single pass needs (at least one workgroup's slot):
+ * about 0.94 * 10^9 bytes in all at n = 10^6 (FP32).  A larger workspace means fewer
  * passes and the same results. */
 size_t hawkes_workspace_bytes(int64_t n, int precision);
 

@@ -114,8 +114,9 @@ constexpr int MAX_SYM_GROUPS = 1024;
 // kernel adds into per-row FP64 accumulators after each pass over at most as
 // many cells as the slot region holds; the default region is this large (or
 // what one pass over every cell needs, if less): with the part linear in n,
-// under 1 GiB of workspace at 10^6 events.
-constexpr size_t DEFAULT_SLOT_BYTES = size_t(768) << 20;
+// under 10^9 bytes of workspace at 10^6 events (the 3072 cells a pass then
+// holds at that size are a whole number of rounds of resident workgroups).
+constexpr size_t DEFAULT_SLOT_BYTES = size_t(704) << 20;
 constexpr int MAX_FUSED_THETA = 2;        // parameter vectors one batched sweep evaluates together
 constexpr int64_t MAX_N = int64_t(1) << 30;
 constexpr double LOG2E = 1.4426950408889634074;

@@ -244,20 +244,15 @@ def run_da_hmc(target: HawkesCutTarget, sur: Surrogate, hmc: HMC, z0, n_iter: in
     return ChainResult(np.array(draws), time.time() - t0, target.n_loglik - n0, target.n_grad - g0, dict(da.stats))
 
 
-def compare(events, county, rect, *, n_burn=1000, n_iter=2000, n_leapfrog=20, seed=2002, lam=1.0, epochs=60,
-            n_warmup=300, log=None, replicate: int = 0) -> dict:
-    """The sampler comparison on one event set.  `replicate` r > 0 repeats it with other random numbers
-    throughout: latent-location draws (Philox seed + 100 r), warm-up and burn-in, surrogate training and the
-    three samplers."""
+def fit_surrogate(rec: "RecordingTarget", lam=1.0, epochs=60, seed=5, log=None):
+    """Trains the surrogate on the recorded (log theta, l, dl/dlog theta, draw) tuples of a burn-in, with 10% of
+    the latent-location draws held out whole; returns the surrogate and its held-out errors.  A draw shifts l by
+    an offset the surrogate does not model, so the value error is measured within each held-out draw, after
+    removing that draw's mean error (the value term of the loss is fitted up to one offset per draw too)."""
     from synth.mlp_init import init_params
 
-    r = int(replicate)
-    target = HawkesCutTarget(events, county, rect, seed=seed + 100 * r, precision="fp32_skip")
-    z0 = np.log(np.array([0.5, 10.0, 7.0, 0.3, 2.0, 0.2]))
-    hmc, st, rec, t_burn = burn_in(target, z0, n_burn, n_leapfrog, seed=1 + r, n_warmup=n_warmup, log=log)
     Zt, Lt, Gt, Ht = np.array(rec.z), np.array(rec.ll), np.array(rec.g), np.array(rec.grp, dtype=np.int64)
     n = Zt.shape[0]
-    # hold out whole latent-location draws (10%); the value fit is up to one offset per draw
     rng = np.random.default_rng(7)
     n_groups = int(Ht.max()) + 1
     held_groups = rng.permutation(n_groups)[: max(1, n_groups // 10)]
@@ -268,26 +263,52 @@ def compare(events, county, rect, *, n_burn=1000, n_iter=2000, n_leapfrog=20, se
     std = Standardiser.fit(Zt[tr], Lt[tr], remap[Ht[tr]])
     t0 = time.time()
     net = SurrogateNet(init_params(3))
-    hist = train(net, std, Zt[tr], Lt[tr], Gt[tr], lam=lam, epochs=epochs, batch=256, lr=1e-3, seed=5 + r, log=log,
+    hist = train(net, std, Zt[tr], Lt[tr], Gt[tr], lam=lam, epochs=epochs, batch=256, lr=1e-3, seed=seed, log=log,
                  groups=remap[Ht[tr]])
     _sync()
     t_train = time.time() - t0
     sur = Surrogate(net, std)
     yh, gh = sur.value_and_grad(Zt[te])
-    # a latent-location draw shifts l by an offset the surrogate does not model: the value error
-    # is measured within each held-out draw, after removing that draw's mean error
     err = yh - Lt[te]
     gte = Ht[te]
     err_c = err - group_means(err, gte)[gte]
     spread_c = Lt[te] - group_means(Lt[te], gte)[gte]
     held = {"tuples": int(n), "draws": n_groups, "held_out_draws": int(held_groups.shape[0]),
-            "train_seconds": t_train, "final_loss": hist[-1],
+            "held_out_tuples": int(te.shape[0]), "train_seconds": t_train, "epochs": epochs, "final_loss": hist[-1],
             "loglik_rmse_within_draw": float(np.sqrt(np.mean(err_c ** 2))),
             "loglik_spread_within_draw": float(np.sqrt(np.mean(spread_c ** 2))),
             "loglik_spread_across_draws": float(Lt[te].std()),
+            "loglik_rel_err_rms": float(np.sqrt(np.mean((err_c / Lt[te]) ** 2))),
             "grad_rel_rmse": float(np.sqrt(np.mean((gh - Gt[te]) ** 2)) / np.sqrt(np.mean(Gt[te] ** 2)))}
     if log:
         log(f"surrogate: {held}")
+    return sur, held
+
+
+def surrogate_fit(events, county, rect, *, n_burn=952, n_leapfrog=20, seed=2002, lam=1.0, epochs=60, n_warmup=300,
+                  log=None) -> dict:
+    """Surrogate training on one event set: exact-HMC burn-in on the cut posterior recording n_burn (n_leapfrog + 1)
+    tuples (952 x 21 = 19,992), then fit_surrogate; returns the held-out errors and the burn-in and training
+    times."""
+    target = HawkesCutTarget(events, county, rect, seed=seed, precision="fp32_skip")
+    z0 = np.log(np.array([0.5, 10.0, 7.0, 0.3, 2.0, 0.2]))
+    hmc, st, rec, t_burn = burn_in(target, z0, n_burn, n_leapfrog, seed=1, n_warmup=n_warmup, log=log)
+    _, held = fit_surrogate(rec, lam=lam, epochs=epochs, seed=5, log=log)
+    return {"burn_in_seconds": t_burn, "step_size": hmc.eps, "n_burn": n_burn, "n_warmup": n_warmup,
+            "surrogate": held}
+
+
+def compare(events, county, rect, *, n_burn=1000, n_iter=2000, n_leapfrog=20, seed=2002, lam=1.0, epochs=60,
+            n_warmup=300, log=None, replicate: int = 0) -> dict:
+    """The sampler comparison on one event set.  `replicate` r > 0 repeats it with other random numbers
+    throughout: latent-location draws (Philox seed + 100 r), warm-up and burn-in, surrogate training and the
+    three samplers."""
+    r = int(replicate)
+    target = HawkesCutTarget(events, county, rect, seed=seed + 100 * r, precision="fp32_skip")
+    z0 = np.log(np.array([0.5, 10.0, 7.0, 0.3, 2.0, 0.2]))
+    hmc, st, rec, t_burn = burn_in(target, z0, n_burn, n_leapfrog, seed=1 + r, n_warmup=n_warmup, log=log)
+    sur, held = fit_surrogate(rec, lam=lam, epochs=epochs, seed=5 + r, log=log)
+    t_train = held["train_seconds"]
     it0 = n_warmup + n_burn + 1
     plain = run_plain_hmc(target, hmc, st.z, n_iter, it0, log=log)
     dah = run_da_hmc(target, sur, hmc, st.z, n_iter, it0 + n_iter + 1, target.prior_var, log=log, seed=11 + r)

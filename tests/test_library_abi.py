@@ -47,8 +47,8 @@ def test_workspace_bytes(lib):
         assert a % 256 == 0 and c % 256 == 0
     # FP32 keeps extra staged source records
     assert lib.hawkes_workspace_bytes(5000, 1) > lib.hawkes_workspace_bytes(5000, 0)
-    # O(n): a part linear in n plus a slot region of at most 768 MiB (under 1 GiB at 10^6 events)
-    assert lib.hawkes_workspace_bytes(1_000_000, 1) < 2**30
+    # O(n): a part linear in n plus a slot region of at most 704 MiB (under 10^9 bytes at 10^6 events)
+    assert lib.hawkes_workspace_bytes(1_000_000, 1) < 10**9
     big = lib.hawkes_workspace_bytes(4_000_000, 1) - lib.hawkes_workspace_bytes(2_000_000, 1)
     assert big < 2_000_000 * 260
     for prec in (0, 1, 2):
