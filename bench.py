@@ -269,13 +269,15 @@ def sampler_costs(args, hk, synth, torch):
 
 
 def run_surrogate_fit(args, hk, synth, torch):
-    """Surrogate training on the 1e5-event workload of the FP32 precision check (1000 days, 3000 counties):
-    exact-HMC burn-in on the cut posterior recording about 20,000 (log theta, l, dl/dlog theta) tuples, 60 epochs
-    of the HIP Sobolev training, and the held-out errors over whole held-out latent-location draws."""
+    """Surrogate training at 1e5 events: exact-HMC burn-in on the cut posterior recording about 20,000
+    (log theta, l, dl/dlog theta) tuples, 60 epochs of the HIP Sobolev training, and the held-out errors over
+    whole held-out latent-location draws."""
     from paper_2407_11349_amd.mcmc.experiment import surrogate_fit
 
-    cfg = synth.N100K
-    ev = synth.generate(cfg)
+    # n100k: the generator of the FP32 precision checks (uniform times); clustered: the branching-process
+    # workload of the sampler comparison at the same size
+    ev = synth.generate(synth.N100K) if args.fit_workload == "n100k" else synth.generate_clustered(n=100_000)
+    cfg = ev.config
     dev = hk.DeviceEvents.from_arrays(ev.t, ev.x, ev.y, ev.s, device="cuda")
     county = torch.from_numpy(ev.county).cuda()
     rect = torch.from_numpy(ev.rect).cuda()
@@ -374,6 +376,8 @@ def main():
                     help="train the surrogate on ~20,000 burn-in tuples of the 1e5-event workload and report its "
                          "held-out error (a few GPU minutes)")
     ap.add_argument("--fit-burn", type=int, default=952, help="burn-in iterations recorded for --surrogate-fit")
+    ap.add_argument("--fit-workload", choices=("n100k", "clustered"), default="n100k",
+                    help="event set of --surrogate-fit")
     ap.add_argument("--sampler-costs", type=int, default=0, metavar="N",
                     help="only time the samplers' exact steps on the clustered workload with N events")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -504,7 +508,7 @@ def main():
     del wsd
 
     if not args.no_fp64:
-        ws64 = hk.Workspace(n, "fp64")
+        ws64 = hk.Workspace(n, "fp64", nbytes=(args.workspace_mib << 20) if args.workspace_mib else None)
         hk.loglik_grad(dev, th, precision="fp64", ws=ws64, out=out_ll, grad=out_g)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
