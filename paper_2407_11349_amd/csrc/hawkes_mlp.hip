@@ -730,16 +730,19 @@ __global__ __launch_bounds__(64 * NWAVE) void k_mlp_train_mfma(MfNet net, const 
     }
 }
 
-// Parameter gradient, contracted over the padded batch:
+// Parameter gradient, contracted over the padded batch, by workgroups of 4 waves:
 //   workgroups 0..511: a 16 x 16 tile of dW2 (0..255) or dW3 (256..511) on the
 //     matrix cores, sum_b h_b[j] a_b[k] + t_b[j] u_b[k], each FP32 factor split
 //     into hi + lo BF16 parts and three products taken (hi hi, hi lo, lo hi;
-//     lo lo is below 2^-16 of the product);
-//   workgroups 512..: one row each of W1 (6 values), b1, b2, b3, w4, then b4
-//     with the loss: lanes take samples lane + 64 i in order, then a fixed
-//     butterfly over the wave.
+//     lo lo is below 2^-16 of the product).  The (term, 32-sample chunk) items
+//     are dealt to the 4 waves in turn, each wave's partial tile is added in
+//     item order, and the 4 partials in wave order;
+//   workgroups 512..: 4 rows each (one per wave) of W1 (6 values), b1, b2, b3,
+//     w4, then b4 with the loss: lanes take samples lane + 64 i in order, then a
+//     fixed butterfly over the wave.
 constexpr int WG_TILES = 512;
 constexpr int WG_ROWS = 5 * H + 1;
+constexpr int WGRAD_WAVES = 4;
 
 // lane group q's 8 values of a 32-sample chunk in the fragment k order
 __device__ inline void load8(const float *p, int q, float4 &x0, float4 &x1)
@@ -754,34 +757,38 @@ __device__ inline void split_pair(const float4 &x0, const float4 &x1, bf16x8 &hi
     split8(x, hi, lo);
 }
 
-__global__ __launch_bounds__(64) void k_mlp_wgrad_mfma(TrainWs ws, int64_t B, float ct, float *__restrict__ grad,
-                                                      float *__restrict__ loss_out)
+__global__ __launch_bounds__(64 * WGRAD_WAVES) void k_mlp_wgrad_mfma(TrainWs ws, int64_t B, float ct,
+                                                                    float *__restrict__ grad,
+                                                                    float *__restrict__ loss_out)
 {
-    const int l = threadIdx.x, q = l >> 4, lm = l & 15;
+    __shared__ f32x4 part[WGRAD_WAVES][64];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, q = l >> 4, lm = l & 15;
     const int64_t bp = ws.bp;
     const int wg = blockIdx.x;
     if (wg < WG_TILES) {
         const int mat = wg >> 8, jt = (wg >> 4) & 15, kt = wg & 15;
         const int vh = mat ? V_H3B : V_H2B, vt = mat ? V_T3B : V_T2B, va = mat ? V_A2 : V_A1, vu = mat ? V_U2 : V_U1;
         const int j = 16 * jt + lm, k = 16 * kt + lm;
+        const int nchunk = int(bp >> 5), nitems = 2 * nchunk;
         f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        for (int term = 0; term < 2; ++term) {
-            const float *pa = ws.vec + (int64_t(term ? vt : vh) * H + j) * bp;
-            const float *pb = ws.vec + (int64_t(term ? vu : va) * H + k) * bp;
-            // four chunks of 32 samples per round, all their loads issued before the products
-            for (int64_t c0 = 0; c0 < bp; c0 += 128) {
-                float4 xa[4][2], xb[4][2];
+        // this wave's items i = w, w + 4, ...: four at a time, all their loads issued before the products
+        for (int i0 = w; i0 < nitems; i0 += 4 * WGRAD_WAVES) {
+            float4 xa[4][2], xb[4][2];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (c0 + 32 * u < bp) {
-                        load8(pa + c0 + 32 * u, q, xa[u][0], xa[u][1]);
-                        load8(pb + c0 + 32 * u, q, xb[u][0], xb[u][1]);
-                    } else {
-                        xa[u][0] = xa[u][1] = xb[u][0] = xb[u][1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                    }
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + WGRAD_WAVES * u;
+                if (i < nitems) {
+                    const int term = (i >= nchunk) ? 1 : 0;
+                    const int64_t c0 = 32 * int64_t(i - term * nchunk);
+                    load8(ws.vec + (int64_t(term ? vt : vh) * H + j) * bp + c0, q, xa[u][0], xa[u][1]);
+                    load8(ws.vec + (int64_t(term ? vu : va) * H + k) * bp + c0, q, xb[u][0], xb[u][1]);
+                } else {
+                    xa[u][0] = xa[u][1] = xb[u][0] = xb[u][1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 }
+            }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 4; ++u) {
+                if (i0 + WGRAD_WAVES * u < nitems) {
                     bf16x8 ah, al, bh, bl;
                     split_pair(xa[u][0], xa[u][1], ah, al);
                     split_pair(xb[u][0], xb[u][1], bh, bl);
@@ -791,17 +798,28 @@ __global__ __launch_bounds__(64) void k_mlp_wgrad_mfma(TrainWs ws, int64_t B, fl
                 }
             }
         }
-        const int64_t base = mat ? OW3 : OW2;
+        part[w][l] = acc;
+        __syncthreads();
+        if (w == 0) {
+            f32x4 t = part[0][l];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            grad[base + int64_t(16 * jt + 4 * q + r) * H + k] = acc[r];
+            for (int ww = 1; ww < WGRAD_WAVES; ++ww)
+                t += part[ww][l];
+            const int64_t base = mat ? OW3 : OW2;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                grad[base + int64_t(16 * jt + 4 * q + r) * H + k] = t[r];
+        }
         return;
     }
-    const int row = wg - WG_TILES;
+    const int row = (wg - WG_TILES) * WGRAD_WAVES + w;
+    if (row >= WG_ROWS)
+        return;
     if (row < H) {  // W1[j][:]: sum_b h1b[j] z_b + t1b[j] r_b
         const float *hb = ws.vec + (int64_t(V_H1B) * H + row) * bp;
         const float *tb = ws.vec + (int64_t(V_T1B) * H + row) * bp;
         float acc[DZ] = {};
+#pragma unroll 4
         for (int64_t b = l; b < bp; b += 64) {
             const float h = hb[b], t = tb[b];
 #pragma unroll
@@ -823,6 +841,7 @@ __global__ __launch_bounds__(64) void k_mlp_wgrad_mfma(TrainWs ws, int64_t B, fl
         const int64_t off = layer == 0 ? OB1 : layer == 1 ? OB2 : OB3;
         const float *hb = ws.vec + (int64_t(vi) * H + j) * bp;
         float acc = 0.0f;
+#pragma unroll 4
         for (int64_t b = l; b < bp; b += 64)
             acc += hb[b];
         acc = wave_sum(acc);
@@ -833,6 +852,7 @@ __global__ __launch_bounds__(64) void k_mlp_wgrad_mfma(TrainWs ws, int64_t B, fl
         const float *a3 = ws.vec + (int64_t(V_A3) * H + j) * bp;
         const float *u3 = ws.vec + (int64_t(V_U3) * H + j) * bp;
         float acc = 0.0f;
+#pragma unroll 4
         for (int64_t b = l; b < bp; b += 64) {
             acc = fmaf(ws.cf[b], a3[b], acc);
             acc = fmaf(ct, u3[b], acc);
@@ -842,6 +862,7 @@ __global__ __launch_bounds__(64) void k_mlp_wgrad_mfma(TrainWs ws, int64_t B, fl
             grad[OW4 + j] = acc;
     } else {  // b4 and the loss
         float acc = 0.0f, ls = 0.0f;
+#pragma unroll 4
         for (int64_t b = l; b < bp; b += 64) {
             acc += ws.cf[b];
             ls += ws.loss[b];
@@ -1058,7 +1079,8 @@ extern "C" int hawkes_mlp_loss_grad(const void *d_state, const float *d_z, const
     hipStream_t st = as_stream(stream);
     hipLaunchKernelGGL(k_mlp_train_mfma, dim3(unsigned(T.bp / 16)), dim3(64 * NWAVE), 0, st, mfnet_of(d_state), d_z, d_y, d_g,
                        batch, lambda_g, t);
-    hipLaunchKernelGGL(k_mlp_wgrad_mfma, dim3(unsigned(WG_TILES + WG_ROWS)), dim3(64), 0, st, t, batch,
+    hipLaunchKernelGGL(k_mlp_wgrad_mfma, dim3(unsigned(WG_TILES + (WG_ROWS + WGRAD_WAVES - 1) / WGRAD_WAVES)),
+                       dim3(64 * WGRAD_WAVES), 0, st, t, batch,
                        2.0f * lambda_g / float(batch), grad, d_loss);
     return check_launch("mlp_loss_grad");
 }
