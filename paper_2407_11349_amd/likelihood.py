@@ -92,7 +92,10 @@ def _workspace(events: DeviceEvents, precision, ws: Workspace | None, stream=Non
     if w is None:
         if len(_WS_CACHE) >= 4:
             _WS_CACHE.clear()
-        w = Workspace(events.n, precision, events.t.device)
+        # allocated on the stream that uses it: torch's caching allocator hands a freed block back only to
+        # later allocations on the same stream, which are ordered after this stream's pending calls
+        with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream()):
+            w = Workspace(events.n, precision, events.t.device)
         _WS_CACHE[key] = w
     return w
 
