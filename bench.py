@@ -329,16 +329,18 @@ def run_campaign(args, hk, synth, torch):
     dev = hk.DeviceEvents.from_arrays(ev.t, ev.x, ev.y, ev.s, device="cuda")
     county = torch.from_numpy(ev.county).cuda()
     rect = torch.from_numpy(ev.rect).cuda()
-    target = HawkesCutTarget(dev, county, rect, seed=2004, precision="fp32_skip",
+    # replicate r > 0: other random numbers throughout (latent-location draws, chains, surrogate training)
+    r = int(args.ess_replicate)
+    target = HawkesCutTarget(dev, county, rect, seed=2004 + 100 * r, precision="fp32_skip",
                              workspace_bytes=(args.workspace_mib << 20) if args.workspace_mib else None)
     cfg = CampaignConfig(n_warmup=args.campaign_warmup, n_plain=args.campaign_plain, n_da=args.ess_iter,
-                         n_leapfrog=20)
-    c = Campaign(args.ess_campaign, target, GPUHooks(log=log), cfg, log=log)
+                         n_leapfrog=20, seed=1 + r)
+    c = Campaign(args.ess_campaign, target, GPUHooks(seed=5 + r, log=log), cfg, log=log)
     phase = c.run(deadline_s=args.deadline_s)
     out = {"metric": "ESS/s surrogate-HMC vs plain HMC", "unit": "ratio", "higher_is_better": True,
            "data": "synthetic", "phase": phase,
            "config": {"workload": ev.config.name, "n_events": ev.n, "step": "resample X + sampler iteration",
-                      **cfg.__dict__},
+                      "replicate": r, **cfg.__dict__},
            "summary": c.summary()}
     with open(os.path.join(args.ess_campaign, "summary.json"), "w") as f:
         json.dump(out, f, indent=1)
