@@ -31,7 +31,8 @@
  *    caller-provided workspace `ws` of hawkes_workspace_bytes() bytes (at
  *    least hawkes_workspace_min_bytes()), 256-byte aligned.  Calls that share a workspace must not overlap; calls
  *    with distinct workspaces are independent (the library keeps no state
- *    between calls other than the calling thread's last-error message).
+ *    between calls other than the calling thread's last-error message and
+ *    the static device array of hawkes_loglik_grad_noalloc).
  *  - `opts` (may be NULL) carries per-call tuning and timing; see
  *    hawkes_options.
  *  - Return value: HAWKES_OK (0) or a negative status; no C++ exception
