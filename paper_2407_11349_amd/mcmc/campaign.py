@@ -127,6 +127,12 @@ class Campaign:
             self.meta, self.arrays = st["meta"], st["arrays"]
             if config is not None and asdict(config) != self.meta["config"]:
                 raise ValueError("the checkpoint was written with another configuration")
+            # iterations logged after the last save are run again: drop their lines
+            log_path = os.path.join(ckpt_dir, "iterations.jsonl")
+            saved = self.meta.get("log_bytes")
+            if saved is not None and os.path.exists(log_path) and os.path.getsize(log_path) > saved:
+                with open(log_path, "r+b") as f:
+                    f.truncate(saved)
         self.cfg = CampaignConfig(**self.meta["config"])
         self._sur = None
 
@@ -136,6 +142,8 @@ class Campaign:
         return self.meta["phase"]
 
     def _save(self):
+        log_path = os.path.join(self.dir, "iterations.jsonl")
+        self.meta["log_bytes"] = os.path.getsize(log_path) if os.path.exists(log_path) else 0
         self.meta["version"] += 1
         save_state(self.dir, {"meta": self.meta, "arrays": {**self.arrays, "_version": self.meta["version"]}})
 

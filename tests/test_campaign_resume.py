@@ -99,3 +99,22 @@ def test_checkpoint_guards(tmp_path):
     json.dump(meta, open(os.path.join(d, "state.json"), "w"))
     with pytest.raises(RuntimeError):
         load_state(d)
+
+
+def test_lines_logged_after_the_last_save_are_dropped_on_resume(tmp_path):
+    """A call that ends between two saves (killed mid-chunk) leaves log lines of iterations the next
+    call runs again: resuming truncates the log to what the checkpoint covers, so every iteration
+    appears once."""
+    d = str(tmp_path / "k")
+    c = Campaign(d, _target(), CPUHooks(), CFG)
+    c.run(max_chunks=3)
+    log_path = os.path.join(d, "iterations.jsonl")
+    n_saved = len(open(log_path).read().splitlines())
+    with open(log_path, "a") as f:  # what an interrupted chunk would have appended
+        f.write(json.dumps({"phase": "warmup", "it": 999}) + "\n")
+    c2 = Campaign(d, _target(), CPUHooks(), CFG)
+    assert len(open(log_path).read().splitlines()) == n_saved
+    assert c2.run() == "done"
+    rows = [json.loads(line) for line in open(log_path)]
+    assert [r["phase"] for r in rows].count("da") == CFG.n_da
+    assert not any(r.get("it") == 999 for r in rows)
