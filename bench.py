@@ -305,7 +305,7 @@ def run_ess(args, hk, synth, torch):
     county = torch.from_numpy(ev.county).cuda()
     rect = torch.from_numpy(ev.rect).cuda()
     out = compare(dev, county, rect, n_burn=args.ess_burn, n_iter=args.ess_iter, n_warmup=args.ess_warmup, log=log,
-                  replicate=args.ess_replicate)
+                  replicate=args.ess_replicate, fallback_prob=args.fallback_prob)
     res = {"metric": "ESS/s surrogate-HMC vs plain HMC", "value": out["ess_per_s_ratio"], "unit": "ratio",
            "higher_is_better": True, "data": "synthetic",
            "config": {"workload": cfg.name, "n_events": ev.n, "burn_in": args.ess_burn, "iterations": args.ess_iter,
@@ -334,7 +334,7 @@ def run_campaign(args, hk, synth, torch):
     target = HawkesCutTarget(dev, county, rect, seed=2004 + 100 * r, precision="fp32_skip",
                              workspace_bytes=(args.workspace_mib << 20) if args.workspace_mib else None)
     cfg = CampaignConfig(n_warmup=args.campaign_warmup, n_plain=args.campaign_plain, n_da=args.ess_iter,
-                         n_leapfrog=20, seed=1 + r)
+                         n_leapfrog=20, seed=1 + r, fallback_prob=args.fallback_prob)
     c = Campaign(args.ess_campaign, target, GPUHooks(seed=5 + r, log=log), cfg, log=log)
     phase = c.run(deadline_s=args.deadline_s)
     out = {"metric": "ESS/s surrogate-HMC vs plain HMC", "unit": "ratio", "higher_is_better": True,
@@ -370,6 +370,9 @@ def main():
     ap.add_argument("--deadline-s", type=float, default=800.0)
     ap.add_argument("--campaign-warmup", type=int, default=150)
     ap.add_argument("--campaign-plain", type=int, default=600)
+    ap.add_argument("--fallback-prob", type=float, default=0.0,
+                    help="DA-HMC exact-HMC fallback: 0 = when the windowed acceptance drops below 0.5 (not "
+                         "invariant in general), q > 0 = an exact-HMC step with fixed probability q (invariant)")
     ap.add_argument("--ess-replicate", type=int, default=0,
                     help="repeat the comparison with other random numbers (latent draws, chains, training)")
     ap.add_argument("--components", action="store_true",

@@ -50,6 +50,7 @@ class CampaignConfig:
     chunk: int = 10           # iterations between checkpoints
     init_eps: float = 0.01
     init_inv_mass: float = 1e-4
+    fallback_prob: float = 0.0  # 0: the windowed-acceptance fallback; q > 0: exact HMC with probability q
 
 
 def _sync():
@@ -296,7 +297,7 @@ class Campaign:
                 return sur.leapfrog(z, p, grad, eps, inv_mass, n, pv)
         da = DelayedAcceptanceHMC(self.target, sur_post, n_leapfrog=self.cfg.n_leapfrog, step_size=self.meta["eps"],
                                   inv_mass=self.arrays["inv_mass"], rng=_rng_from(self.meta["rng"]),
-                                  trajectory=traj, jitter=self.cfg.jitter)
+                                  trajectory=traj, jitter=self.cfg.jitter, fallback_prob=self.cfg.fallback_prob)
         d = self.meta["da"]
         da.window = deque(d["window"], maxlen=da.window.maxlen)
         if d["stats"] is not None:

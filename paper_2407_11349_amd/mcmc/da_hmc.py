@@ -6,9 +6,21 @@ s(z) = lhat(z) + log prior(z) is accepted with min(1, exp(H_s(z, p) - H_s(z', p'
 H_s = -s + kinetic.  Stage 2: the exact log posterior corrects it with
 min(1, exp([logp(z') - s(z')] - [logp(z) - s(z)])).  The composite kernel
 leaves the exact posterior invariant whatever the surrogate's error; the
-surrogate only changes how often proposals survive.  When the acceptance rate
-over the last `window` iterations falls below `fallback_below`, iterations are
-exact HMC (exact gradients) until it recovers.
+surrogate only changes how often proposals survive.
+
+Exact-HMC fallback, two rules:
+  window   (fallback_prob = 0) when the acceptance rate over the last `window`
+           iterations falls below `fallback_below`, iterations are exact HMC
+           (exact gradients) until it recovers.  The choice of kernel then
+           depends on the chain's recent past, and through it on where the
+           chain is: where the surrogate is poor, acceptance drops and exact
+           HMC takes over.  Each kernel leaves the posterior invariant, but a
+           choice that follows the state does not in general: with a surrogate
+           that is poor in one half-space the chain under-visits that half
+           (tests/test_samplers.py).
+  mixture  (fallback_prob = q > 0) each iteration is an exact-HMC step with the
+           fixed probability q and a delayed-acceptance step otherwise; a fixed
+           mixture of invariant kernels is invariant.
 
 Under the cut posterior the target changes with every latent-location draw, so
 the exact value at the current point is needed afresh each iteration, but only
@@ -37,9 +49,13 @@ class DAState:
 
 class DelayedAcceptanceHMC:
     def __init__(self, target, surrogate_logp_and_grad, dim=6, n_leapfrog=20, step_size=0.05, inv_mass=None,
-                 rng=None, window=50, fallback_below=0.5, trajectory=None, jitter=0.0):
+                 rng=None, window=50, fallback_below=0.5, trajectory=None, jitter=0.0, fallback_prob=0.0):
         """trajectory(z, p, grad, eps, inv_mass, n_steps) -> (z, p, s, grad), if given, runs the whole stage-1
-        leapfrog trajectory on the surrogate at once (e.g. on the GPU) instead of step by step here."""
+        leapfrog trajectory on the surrogate at once (e.g. on the GPU) instead of step by step here.
+        fallback_prob > 0 selects the mixture fallback rule (module docstring) instead of the window rule."""
+        if not (0.0 <= fallback_prob < 1.0):
+            raise ValueError("fallback_prob must be in [0, 1)")
+        self.fallback_prob = float(fallback_prob)
         self.target = target
         self.sur = surrogate_logp_and_grad
         self.trajectory = trajectory
@@ -82,7 +98,8 @@ class DelayedAcceptanceHMC:
 
     def step(self, st: DAState):
         self.stats["iterations"] += 1
-        if self.in_fallback():
+        use_exact = (self.rng.uniform() < self.fallback_prob) if self.fallback_prob > 0.0 else self.in_fallback()
+        if use_exact:
             self.stats["fallback"] += 1
             self.exact.eps = self.eps
             self.exact.inv_mass = self.inv_mass

@@ -216,7 +216,7 @@ def run_mh(target: HawkesCutTarget, z0, inv_mass, n_iter: int, it0: int, n_adapt
 
 
 def run_da_hmc(target: HawkesCutTarget, sur: Surrogate, hmc: HMC, z0, n_iter: int, it0: int, prior_var: float,
-               log=None, seed=11) -> ChainResult:
+               log=None, seed=11, fallback_prob=0.0) -> ChainResult:
     def sur_post(z):
         ll, g = sur.value_and_grad(z)
         return float(ll[0]) - 0.5 * float(np.dot(z, z)) / prior_var, g[0] - np.asarray(z) / prior_var
@@ -226,7 +226,8 @@ def run_da_hmc(target: HawkesCutTarget, sur: Surrogate, hmc: HMC, z0, n_iter: in
 
     da = DelayedAcceptanceHMC(target, sur_post, n_leapfrog=hmc.n_leapfrog, step_size=hmc.eps,
                               inv_mass=hmc.inv_mass, rng=np.random.default_rng(seed),
-                              trajectory=trajectory if hasattr(sur, "leapfrog") else None, jitter=STEP_JITTER)
+                              trajectory=trajectory if hasattr(sur, "leapfrog") else None, jitter=STEP_JITTER,
+                              fallback_prob=fallback_prob)
     n0, g0 = target.n_loglik, target.n_grad
     _sync()
     t0 = time.time()
@@ -299,7 +300,7 @@ def surrogate_fit(events, county, rect, *, n_burn=952, n_leapfrog=20, seed=2002,
 
 
 def compare(events, county, rect, *, n_burn=1000, n_iter=2000, n_leapfrog=20, seed=2002, lam=1.0, epochs=60,
-            n_warmup=300, log=None, replicate: int = 0) -> dict:
+            n_warmup=300, log=None, replicate: int = 0, fallback_prob: float = 0.0) -> dict:
     """The sampler comparison on one event set.  `replicate` r > 0 repeats it with other random numbers
     throughout: latent-location draws (Philox seed + 100 r), warm-up and burn-in, surrogate training and the
     three samplers."""
@@ -311,7 +312,8 @@ def compare(events, county, rect, *, n_burn=1000, n_iter=2000, n_leapfrog=20, se
     t_train = held["train_seconds"]
     it0 = n_warmup + n_burn + 1
     plain = run_plain_hmc(target, hmc, st.z, n_iter, it0, log=log)
-    dah = run_da_hmc(target, sur, hmc, st.z, n_iter, it0 + n_iter + 1, target.prior_var, log=log, seed=11 + r)
+    dah = run_da_hmc(target, sur, hmc, st.z, n_iter, it0 + n_iter + 1, target.prior_var, log=log, seed=11 + r,
+                     fallback_prob=fallback_prob)
     mh = run_mh(target, st.z, hmc.inv_mass, n_iter, it0 + 2 * n_iter + 2, log=log, seed=13 + r)
     out = {"burn_in_seconds": t_burn, "surrogate": held, "step_size": hmc.eps, "n_iter": n_iter, "replicate": r}
     for name, r in (("plain_hmc", plain), ("da_hmc", dah), ("univariate_mh", mh)):

@@ -242,3 +242,46 @@ def test_step_size_jitter_breaks_a_resonant_trajectory_length():
     assert bulk_ess(stuck[:, 0].reshape(1, -1)) < 20  # creeps along with the leapfrog's period error
     assert bulk_ess(mixed[:, 0].reshape(1, -1)) > 300
     _check_moments(mixed, np.zeros(6), np.eye(6))
+
+
+def test_windowed_fallback_follows_the_state_and_biases_a_fixed_mixture_does_not():
+    """The exact-HMC fallback chosen by recent acceptance depends on where the chain is: with a
+    surrogate that is exact for z0 < 0 and far too narrow in z0 for z0 >= 0, acceptance drops on the
+    right, exact HMC takes over there, and the chain under-visits the right half (a biased mean and
+    a shrunken variance of z0 under a standard normal target).  An exact-HMC step taken with a fixed
+    probability each iteration is a fixed mixture of invariant kernels and samples the target."""
+
+    class Std:
+        prior_var = 1e4
+
+        def logp(self, z):
+            return -0.5 * float(z @ z)
+
+        def logp_and_grad(self, z):
+            return -0.5 * float(z @ z), -z
+
+    def sur(z):
+        if z[0] < 0:
+            return -0.5 * float(z @ z), -z.copy()
+        g = -z.copy()
+        g[0] -= 4.0 * z[0]
+        return -0.5 * float(z @ z) - 2.0 * z[0] ** 2, g
+
+    def run(**kw):
+        da = DelayedAcceptanceHMC(Std(), sur, dim=2, n_leapfrog=8, step_size=0.25, rng=np.random.default_rng(11),
+                                  window=50, **kw)
+        st = da.init_state(np.zeros(2))
+        d = np.empty((20000, 2))
+        for i in range(d.shape[0]):
+            st, _, _ = da.step(st)
+            d[i] = st.z
+        return d[:, 0], da.stats
+
+    z0, stats = run(fallback_below=0.5)
+    assert stats["fallback"] > 0
+    assert z0.mean() < -8 * mcse_mean(z0[None, :]) and z0.var() < 0.8
+    z0, stats = run(fallback_below=0.5, fallback_prob=0.2)
+    assert stats["fallback"] > 0
+    assert abs(z0.mean()) < 4 * mcse_mean(z0[None, :]) and abs(z0.var() - 1.0) < 0.1
+    with pytest.raises(ValueError):
+        DelayedAcceptanceHMC(Std(), sur, dim=2, fallback_prob=1.0)
