@@ -18,12 +18,15 @@ from paper_2407_11349_amd.mcmc.cut import HawkesCutTarget
 pytestmark = pytest.mark.gpu
 
 
-def test_trained_surrogate_beats_plain_hmc_at_equal_accuracy(tmp_path):
+@pytest.mark.parametrize("fallback_prob", [0.0, 0.05])
+def test_trained_surrogate_beats_plain_hmc_at_equal_accuracy(tmp_path, fallback_prob):
+    """fallback_prob 0: the windowed exact-HMC fallback; 0.05: the fixed-mixture fallback."""
     ev = synth.generate_clustered(n=20_000, seed=1201)
     dev = hk.DeviceEvents.from_arrays(ev.t, ev.x, ev.y, ev.s)
     target = HawkesCutTarget(dev, torch.from_numpy(ev.county).cuda(), torch.from_numpy(ev.rect).cuda(), seed=2201,
                              precision="fp32_skip")
-    cfg = CampaignConfig(n_warmup=120, n_plain=400, n_da=400, n_leapfrog=20, seed=7, chunk=100)
+    cfg = CampaignConfig(n_warmup=120, n_plain=400, n_da=400, n_leapfrog=20, seed=7, chunk=100,
+                         fallback_prob=fallback_prob)
     c = Campaign(str(tmp_path / "run"), target, GPUHooks(epochs=30, log=None), cfg,
                  log=lambda m: print(m, flush=True))
     assert c.run() == "done"
