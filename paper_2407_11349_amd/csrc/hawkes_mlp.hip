@@ -481,75 +481,191 @@ __device__ inline void stage_small(const uint16_t *__restrict__ w, SmallW &sw)
     __syncthreads();
 }
 
-// Value and input gradient of 16 samples per workgroup of 8 waves.
+// Several sample tiles per workgroup (inference): NS tiles of 16 samples share
+// every weight fragment a wave loads, so each fragment feeds 2 NS MFMAs; the
+// column operands of the NS tiles sit side by side in LDS.
+template <int NS>
+using OperandsN = bf16x8[2][NS][8][2][64];
+
+template <int NS>
+__device__ inline void mf_product_n(const Frags &a, const float (*x)[VPL], float (*y)[VPL], OperandsN<NS> &op, int slot)
+{
+    static_assert(RT == 2, "one published chunk per wave");
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        bf16x8 hi, lo;
+        split8(x[s], hi, lo);
+        op[slot][s][w][0][l] = hi;
+        op[slot][s][w][1][l] = lo;
+    }
+    __syncthreads();
+    f32x4 acc[NS][RT];
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+            acc[s][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kc = 0; kc < 8; ++kc) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const bf16x8 bh = op[slot][s][kc][0][l], bl = op[slot][s][kc][1][l];
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[kc][t], bl, acc[s][t], 0, 0, 0);
+                acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[kc][t], bh, acc[s][t], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                y[s][4 * t + r] = acc[s][t][r];
+}
+
+// sample_sums for NS tiles: sample 16 s + l % 16 of the workgroup
+template <int NS>
+__device__ inline void sample_sums_n(float (*v)[NRED], float (*red)[16 * NS][NRED])
+{
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int k = 0; k < NRED; ++k)
+            v[s][k] = group_sum(v[s][k]);
+    if (l < 16)
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int k = 0; k < NRED; ++k)
+                red[w][16 * s + l][k] = v[s][k];
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int k = 0; k < NRED; ++k) {
+            float t = red[0][16 * s + (l & 15)][k];
+#pragma unroll
+            for (int ww = 1; ww < NWAVE; ++ww)
+                t += red[ww][16 * s + (l & 15)][k];
+            v[s][k] = t;
+        }
+}
+
+// Value and input gradient of 16 NS samples per workgroup of 8 waves.
+constexpr int FWD_TILES = 2;
+template <int NS>
 __global__ __launch_bounds__(64 * NWAVE) void k_mlp_forward_mfma(MfNet net, const float *__restrict__ z, int64_t B,
                                                          float *__restrict__ f_out, float *__restrict__ gz_out)
 {
     __shared__ SmallW sw;
-    __shared__ Operands op;
-    __shared__ float red[NWAVE][16][NRED];
+    __shared__ OperandsN<NS> op;
+    __shared__ float red[NWAVE][16 * NS][NRED];
+    __shared__ float4 slope[2][NS][NWAVE][VPL / 4][64];  // GELU slopes of layers 1 and 2, until the reverse pass
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, q = l >> 4;
-    const int64_t b = int64_t(blockIdx.x) * 16 + (l & 15);
-    const bool valid = b < B;
-    stage_small(net.w, sw);
-    float zi[DZ];
+    int64_t b[NS];
+    bool valid[NS];
 #pragma unroll
-    for (int d = 0; d < DZ; ++d)
-        zi[d] = valid ? z[b * DZ + d] : 0.0f;
-    float v[VPL], y[VPL], s1[VPL], s2[VPL];
+    for (int s = 0; s < NS; ++s) {
+        b[s] = int64_t(blockIdx.x) * (16 * NS) + 16 * s + (l & 15);
+        valid[s] = b[s] < B;
+    }
+    stage_small(net.w, sw);
+    float zi[NS][DZ];
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int d = 0; d < DZ; ++d)
+            zi[s][d] = valid[s] ? z[b[s] * DZ + d] : 0.0f;
+    float v[NS][VPL], y[NS][VPL];
+    auto put_slope = [&](int layer, int s, int i4, float x0, float x1, float x2, float x3) {
+        slope[layer][s][w][i4][l] = make_float4(x0, x1, x2, x3);
+    };
     Frags a;
     load_frags(net.frag[F_W2], a);
 #pragma unroll
-    for (int i = 0; i < VPL; ++i) {
-        const int f = feat(w, q, i);
-        float h = sw.b1[f];
+    for (int s = 0; s < NS; ++s)
 #pragma unroll
-        for (int d = 0; d < DZ; ++d)
-            h = fmaf(sw.w1[d][f], zi[d], h);
-        v[i] = gelu(h);
-        s1[i] = gelu_d1(h);
-    }
-    mf_product(a, v, y, op, 0);
-    load_frags(net.frag[F_W3], a);
-#pragma unroll
-    for (int i = 0; i < VPL; ++i) {
-        const float h = y[i] + sw.b2[feat(w, q, i)];
-        v[i] = gelu(h);
-        s2[i] = gelu_d1(h);
-    }
-    mf_product(a, v, y, op, 1);
-    load_frags(net.frag[F_W3T], a);
-    float acc[NRED] = {};
-#pragma unroll
-    for (int i = 0; i < VPL; ++i) {
-        const int f = feat(w, q, i);
-        const float h = y[i] + sw.b3[f];
-        acc[0] = fmaf(sw.w4[f], gelu(h), acc[0]);
-        v[i] = sw.w4[f] * gelu_d1(h);
-    }
-    // input gradient: d2 = s2 (W3^T d3), d1 = s1 (W2^T d2), g = W1^T d1
-    mf_product(a, v, y, op, 0);
-    load_frags(net.frag[F_W2T], a);
-#pragma unroll
-    for (int i = 0; i < VPL; ++i)
-        v[i] = y[i] * s2[i];
-    mf_product(a, v, y, op, 1);
-#pragma unroll
-    for (int i = 0; i < VPL; ++i) {
-        const int f = feat(w, q, i);
-        const float d1 = y[i] * s1[i];
-#pragma unroll
-        for (int d = 0; d < DZ; ++d)
-            acc[1 + d] = fmaf(sw.w1[d][f], d1, acc[1 + d]);
-    }
-    sample_sums(acc, red);
-    if (w == 0 && q == 0 && valid) {
-        f_out[b] = acc[0] + bf16_to_f32(net.w[OB4]);
-        if (gz_out)
+        for (int i = 0; i < VPL; ++i) {
+            const int f = feat(w, q, i);
+            float h = sw.b1[f];
 #pragma unroll
             for (int d = 0; d < DZ; ++d)
-                gz_out[b * DZ + d] = acc[1 + d];
-    }
+                h = fmaf(sw.w1[d][f], zi[s][d], h);
+            v[s][i] = gelu(h);
+            y[s][i] = gelu_d1(h);
+        }
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int i4 = 0; i4 < VPL / 4; ++i4)
+            put_slope(0, s, i4, y[s][4 * i4], y[s][4 * i4 + 1], y[s][4 * i4 + 2], y[s][4 * i4 + 3]);
+    mf_product_n<NS>(a, v, y, op, 0);
+    load_frags(net.frag[F_W3], a);
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) {
+            const float h = y[s][i] + sw.b2[feat(w, q, i)];
+            v[s][i] = gelu(h);
+            y[s][i] = gelu_d1(h);
+        }
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int i4 = 0; i4 < VPL / 4; ++i4)
+            put_slope(1, s, i4, y[s][4 * i4], y[s][4 * i4 + 1], y[s][4 * i4 + 2], y[s][4 * i4 + 3]);
+    mf_product_n<NS>(a, v, y, op, 1);
+    load_frags(net.frag[F_W3T], a);
+    float acc[NS][NRED] = {};
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) {
+            const int f = feat(w, q, i);
+            const float h = y[s][i] + sw.b3[f];
+            acc[s][0] = fmaf(sw.w4[f], gelu(h), acc[s][0]);
+            v[s][i] = sw.w4[f] * gelu_d1(h);
+        }
+    // input gradient: d2 = s2 (W3^T d3), d1 = s1 (W2^T d2), g = W1^T d1
+    mf_product_n<NS>(a, v, y, op, 0);
+    load_frags(net.frag[F_W2T], a);
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) {
+            const float4 g = slope[1][s][w][i >> 2][l];
+            const float sl[4] = {g.x, g.y, g.z, g.w};
+            v[s][i] = y[s][i] * sl[i & 3];
+        }
+    mf_product_n<NS>(a, v, y, op, 1);
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) {
+            const int f = feat(w, q, i);
+            const float4 g = slope[0][s][w][i >> 2][l];
+            const float sl[4] = {g.x, g.y, g.z, g.w};
+            const float d1 = y[s][i] * sl[i & 3];
+#pragma unroll
+            for (int d = 0; d < DZ; ++d)
+                acc[s][1 + d] = fmaf(sw.w1[d][f], d1, acc[s][1 + d]);
+        }
+    sample_sums_n<NS>(acc, red);
+    if (w == 0 && q == 0)
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            if (valid[s]) {
+                f_out[b[s]] = acc[s][0] + bf16_to_f32(net.w[OB4]);
+                if (gz_out)
+#pragma unroll
+                    for (int d = 0; d < DZ; ++d)
+                        gz_out[b[s] * DZ + d] = acc[s][1 + d];
+            }
 }
 
 // Training pass.  Per-sample vectors of the parameter gradient, feature-major
@@ -1041,8 +1157,8 @@ extern "C" int hawkes_mlp_forward(const void *d_state, const float *d_z, int64_t
         hipLaunchKernelGGL(k_mlp_forward, dim3(unsigned(batch)), dim3(H), 0, as_stream(stream), net_of(d_state), d_z,
                            batch, d_f, d_gz);
     else
-        hipLaunchKernelGGL(k_mlp_forward_mfma, dim3(unsigned((batch + 15) / 16)), dim3(64 * NWAVE), 0,
-                           as_stream(stream),
+        hipLaunchKernelGGL(k_mlp_forward_mfma<FWD_TILES>, dim3(unsigned((batch + 16 * FWD_TILES - 1) / (16 * FWD_TILES))),
+                           dim3(64 * NWAVE), 0, as_stream(stream),
                            mfnet_of(d_state), d_z, batch, d_f, d_gz);
     return check_launch("mlp_forward");
 }
