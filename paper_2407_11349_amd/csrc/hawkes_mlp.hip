@@ -14,7 +14,9 @@
 // Batched kernels (value and input gradient of many inputs, the training
 // pass) run the 256 x 256 products on the matrix cores with
 // v_mfma_f32_16x16x32_bf16, features as rows and 16 samples as columns, a
-// workgroup of 8 waves per 16 samples (2 row tiles per wave).  A product's
+// workgroup of 8 waves per tile of 16 samples (2 row tiles per wave; batched
+// inference takes two sample tiles per workgroup, so every weight fragment a
+// wave loads feeds both).  A product's
 // FP32 output sits in the lanes in the k order of the next product's column
 // operand, so each wave converts its own outputs and the operands meet in
 // LDS.  The weights are exact BF16; each FP32 activation enters as hi + lo
