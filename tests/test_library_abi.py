@@ -154,3 +154,21 @@ def test_mlp_leapfrog_host_validation(lib):
     assert lib.hawkes_mlp_leapfrog(fake, fake, 0, None) == -1
     assert lib.hawkes_mlp_leapfrog(fake, fake, 4097, None) == -1
     assert _lib.LEAPFROG_IO_DOUBLES * 8 == 336
+
+
+def _declared_arity():
+    """Parameter count of every function the headers declare (a `(void)` list counts as none)."""
+    arity = {}
+    for h in sorted(glob.glob(os.path.join(INCLUDE, "*.h"))):
+        src = re.sub(r"/\*.*?\*/|//[^\n]*", "", open(h).read(), flags=re.S)
+        for name, params in re.findall(r"\b(hawkes_[a-z0-9_]+)\s*\(([^;{)]*)\)\s*;", src):
+            params = " ".join(params.split())
+            arity[name] = 0 if params in ("", "void") else params.count(",") + 1
+    return arity
+
+
+def test_binding_argument_counts_match_the_headers(lib):
+    arity = _declared_arity()
+    assert set(arity) == set(_declared())
+    for name, n in arity.items():
+        assert len(getattr(lib, name).argtypes) == n, name
