@@ -11,7 +11,8 @@ the FP32 skip mode (same result without the exactly-zero background terms;
 reported apart, never as the O(N^2) metric), the forward-only sweep for one
 and for two parameter vectors, the roofline of the dominant kernel (pair
 sweep), the path's smaller steps (latent-location draw, surrogate inference
-and training step), and the FP64 CPU oracle timed on a bounded sample of
+and training step), a reduced live run of the surrogate-HMC vs plain-HMC
+comparison (ESS/s), and the FP64 CPU oracle timed on a bounded sample of
 target rows on the host cores.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1]
@@ -315,6 +316,43 @@ def run_ess(args, hk, synth, torch):
     print(json.dumps(res), flush=True)
 
 
+def ess_reduced(hk, synth, torch) -> dict:
+    """The sampler comparison, reduced so that it runs live in the default bench (about 10 s): a clustered
+    event set of 2 * 10^4 events, FP32 skip-mode likelihood with X redrawn every iteration, 120 exact-HMC
+    warm-up iterations, 400 plain exact-gradient HMC iterations whose gradient evaluations train the BF16
+    surrogate (30 epochs), then 400 delayed-acceptance HMC iterations driven by it (20 leapfrog steps, exact
+    fallback below windowed acceptance 0.5).  ESS/s = min over the six parameters of bulk-ESS / chain seconds.
+    The same code runs the comparison at 10^6 events as a checkpointed campaign (--ess-campaign)."""
+    import tempfile
+
+    from paper_2407_11349_amd.mcmc.campaign import Campaign, CampaignConfig, GPUHooks
+    from paper_2407_11349_amd.mcmc.cut import HawkesCutTarget
+
+    ev = synth.generate_clustered(n=20_000, seed=1201)
+    dev = hk.DeviceEvents.from_arrays(ev.t, ev.x, ev.y, ev.s, device="cuda")
+    target = HawkesCutTarget(dev, torch.from_numpy(ev.county).cuda(), torch.from_numpy(ev.rect).cuda(), seed=2201,
+                             precision="fp32_skip")
+    cfg = CampaignConfig(n_warmup=120, n_plain=400, n_da=400, n_leapfrog=20, seed=7, chunk=100)
+    with tempfile.TemporaryDirectory() as d:
+        c = Campaign(os.path.join(d, "run"), target, GPUHooks(epochs=30, log=None), cfg, log=lambda m: None)
+        phase = c.run()
+        s = c.summary()
+    if phase != "done":
+        raise RuntimeError(f"reduced sampler comparison ended in phase {phase}")
+    return {"workload": ev.config.name, "n_events": ev.n,
+            "iterations": {"warmup": cfg.n_warmup, "plain_hmc": cfg.n_plain, "da_hmc": cfg.n_da},
+            "leapfrog": cfg.n_leapfrog,
+            "plain_hmc_ess_per_s": s["plain_hmc"]["ess_per_s"], "da_hmc_ess_per_s": s["da_hmc"]["ess_per_s"],
+            "ess_per_s_ratio": s["ess_per_s_ratio"],
+            "ess_per_s_ratio_incl_training": s["ess_per_s_ratio_incl_training"],
+            "max_mean_diff_in_combined_mcse": s["max_mean_diff_in_combined_mcse"],
+            "means_agree_within_3_mcse": s["means_agree_within_3_mcse"], "max_rhat": s["max_rhat"],
+            "seconds": s["seconds"],
+            "note": "live, reduced: 2e4 events and 400 + 400 iterations; the comparison at 1e6 events "
+                    "(2,000 DA-HMC iterations) is a multi-hour campaign checkpointed over several runs "
+                    "(bench.py --ess-campaign)"}
+
+
 def run_campaign(args, hk, synth, torch):
     """The comparison of plain HMC and surrogate DA-HMC at 1e6 events as a resumable campaign: continues the
     run checkpointed in args.ess_campaign until the deadline, saves, and prints the summary so far.  Workload:
@@ -359,6 +397,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-skip", action="store_true", help="do not time the FP32 skip mode")
+    ap.add_argument("--no-ess", action="store_true", help="do not run the reduced sampler comparison")
     ap.add_argument("--ess", action="store_true",
                     help="run the surrogate-HMC vs plain-HMC ESS/s comparison instead (minutes of GPU time)")
     ap.add_argument("--ess-n", type=int, default=100_000, help="events of the ESS comparison workload")
@@ -594,6 +633,17 @@ def main():
     log(f"resample {comp['resample']['us_per_call']:.1f} us ({comp['resample']['achieved_gbs']:.0f} GB/s); "
         f"mlp forward batch 1 {comp['mlp_forward']['batch1_us']:.1f} us, batch 21000 "
         f"{comp['mlp_forward']['batch21000_ms']:.2f} ms; train step {comp['mlp_train_step']['ms_per_step']:.3f} ms")
+
+    if not args.no_ess:
+        log("reduced sampler comparison (2e4 events) ...")
+        try:
+            result["ess_reduced"] = ess_reduced(hk, synth, torch)
+            e = result["ess_reduced"]
+            log(f"ESS/s DA-HMC {e['da_hmc_ess_per_s']:.1f} vs plain HMC {e['plain_hmc_ess_per_s']:.1f}: ratio "
+                f"{e['ess_per_s_ratio']:.2f}, means within {e['max_mean_diff_in_combined_mcse']:.2f} MCSE")
+        except Exception as exc:  # reported in the line; the headline figures above stand on their own
+            log(f"reduced sampler comparison failed: {exc!r}")
+            result["ess_reduced"] = {"error": repr(exc)}
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
