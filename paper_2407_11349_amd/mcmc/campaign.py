@@ -126,6 +126,8 @@ class Campaign:
             self.arrays = {"z": z0.copy()}
         else:
             self.meta, self.arrays = st["meta"], st["arrays"]
+            # a field added to CampaignConfig after the checkpoint was written takes its default
+            self.meta["config"] = {**asdict(CampaignConfig()), **self.meta["config"]}
             if config is not None and asdict(config) != self.meta["config"]:
                 raise ValueError("the checkpoint was written with another configuration")
             # iterations logged after the last save are run again: drop their lines

@@ -118,3 +118,19 @@ def test_lines_logged_after_the_last_save_are_dropped_on_resume(tmp_path):
     rows = [json.loads(line) for line in open(log_path)]
     assert [r["phase"] for r in rows].count("da") == CFG.n_da
     assert not any(r.get("it") == 999 for r in rows)
+
+
+def test_checkpoint_from_before_a_new_config_field_resumes(tmp_path):
+    """A checkpoint written before CampaignConfig gained a field (here fallback_prob) resumes with the
+    field's default, under the explicit configuration too, and finishes like a fresh run."""
+    d = str(tmp_path / "old")
+    Campaign(d, _target(), CPUHooks(), CFG).run(max_chunks=2)
+    meta = json.load(open(os.path.join(d, "state.json")))
+    del meta["config"]["fallback_prob"]
+    json.dump(meta, open(os.path.join(d, "state.json"), "w"))
+    c = Campaign(d, _target(), CPUHooks(), CFG)
+    assert c.cfg == CFG
+    assert c.run() == "done"
+    ref = str(tmp_path / "ref")
+    Campaign(ref, _target(), CPUHooks(), CFG).run()
+    assert np.array_equal(load_state(d)["arrays"]["da_draws"], load_state(ref)["arrays"]["da_draws"])
