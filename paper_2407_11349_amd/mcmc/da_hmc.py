@@ -36,7 +36,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from .hmc import HMC, HMCState, accept_prob, check_state, kinetic, leapfrog
+from .hmc import HMC, accept_prob, check_state, kinetic, leapfrog
 
 
 @dataclass

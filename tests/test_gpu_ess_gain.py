@@ -6,7 +6,6 @@ by it.  The surrogate chain must reach more effective samples per second than th
 while its posterior means agree with the plain chain's within 3 combined Monte Carlo standard
 errors (every draw is seeded: the outcome is reproducible; only the seconds vary)."""
 
-import numpy as np
 import pytest
 import torch
 

@@ -4,7 +4,6 @@ accumulators in a fixed cell order, so results must be bitwise the same whatever
 size (one pass, several, or one workgroup per pass), for the symmetric sweep, the row sweep and
 the two-vector sweep, at FP32 and FP64.  A workspace below the minimum is refused."""
 
-import ctypes
 
 import numpy as np
 import pytest
