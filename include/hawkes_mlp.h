@@ -56,8 +56,9 @@ int hawkes_mlp_store(const void *d_state, float *d_params, void *stream);
 /* Value and input gradient for `batch` inputs: d_z[batch][6] ->
  * d_f[batch], d_gz[batch][6] (d_gz may be NULL).  Batches of up to 8 inputs
  * take the one-sample kernel, whose arithmetic is that of
- * hawkes_mlp_leapfrog; larger batches take the matrix cores, 16 inputs per
- * wave.  The two agree to ~1e-5 relative, not bitwise. */
+ * hawkes_mlp_leapfrog; larger batches take the matrix cores (a workgroup of
+ * 8 waves per two tiles of 16 inputs).  The two agree to ~1e-5 relative, not
+ * bitwise. */
 int hawkes_mlp_forward(const void *d_state, const float *d_z, int64_t batch, float *d_f, float *d_gz,
                        void *stream);
 
