@@ -152,7 +152,10 @@ size_t hawkes_workspace_bytes(int64_t n, int precision);
  * Between this and hawkes_workspace_bytes() the results are the same and
  * only the number of passes changes.  Options that enlarge a workgroup's
  * slot (fewer symmetric groups) may need more: such calls return
- * HAWKES_EWORKSPACE. */
+ * HAWKES_EWORKSPACE.  The minimum does not decrease with n, so a workspace
+ * sized for n events (by either function) serves every smaller event set;
+ * hawkes_workspace_bytes() itself is not monotone in n (its single-pass
+ * size follows the group structure of the sweep). */
 size_t hawkes_workspace_min_bytes(int64_t n, int precision);
 
 /* Log-likelihood of rows [row_begin, row_end):  *d_loglik = sum_n l_n

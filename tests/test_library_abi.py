@@ -7,6 +7,7 @@ import glob
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2407_11349_amd import _lib
@@ -172,3 +173,16 @@ def test_binding_argument_counts_match_the_headers(lib):
     assert set(arity) == set(_declared())
     for name, n in arity.items():
         assert len(getattr(lib, name).argtypes) == n, name
+
+
+def test_a_workspace_sized_for_n_events_serves_every_smaller_set(lib):
+    """The minimum is non-decreasing in n and never above the default, and the default's slot region is
+    at most 704 MiB over the minimum's linear part, over sizes from 1 to 2 * 10^7 events."""
+    ns = sorted(set(int(v) for v in np.logspace(0, 7.3, 1500)) | {511, 512, 513, 65535, 65536, 65537})
+    for prec in (0, 1, 2):
+        prev = 0
+        for n in ns:
+            lo, hi = lib.hawkes_workspace_min_bytes(n, prec), lib.hawkes_workspace_bytes(n, prec)
+            assert prev <= lo <= hi, (prec, n)
+            assert hi <= lo + (704 << 20) + 256, (prec, n)
+            prev = lo
