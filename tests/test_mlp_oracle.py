@@ -139,3 +139,20 @@ def test_bf16_rounding_rule():
     assert r[4] == 1.0 + 2**-6  # tie between 1 + 2^-7 (odd) and 1 + 2^-6 (even)
     ref = torch.tensor(vals).to(torch.bfloat16).to(torch.float64).numpy()
     np.testing.assert_array_equal(r, ref)
+
+
+def test_gelu_and_its_derivatives():
+    """GELU(x) = x Phi(x) against scipy's normal cdf, and its first and second derivatives against
+    Richardson-extrapolated central differences of the function itself (a mistake in a derivative
+    formula, such as a dropped x phi(x) term, fails here before it reaches the Sobolev gradient)."""
+    from scipy.stats import norm
+
+    x = np.linspace(-7.0, 7.0, 281)
+    np.testing.assert_allclose(mlp.gelu(x), x * norm.cdf(x), rtol=1e-14, atol=1e-15)  # 1 + erf cancels far left
+
+    def rich(f, h):
+        d = lambda s: (f(x + s) - f(x - s)) / (2 * s)  # noqa: E731
+        return (4 * d(h / 2) - d(h)) / 3
+
+    np.testing.assert_allclose(mlp.gelu_d1(x), rich(mlp.gelu, 1e-3), rtol=1e-9, atol=1e-11)
+    np.testing.assert_allclose(mlp.gelu_d2(x), rich(mlp.gelu_d1, 1e-3), rtol=1e-8, atol=1e-10)
